@@ -20,6 +20,8 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-s
 FLAG_BANK_ORDER = 1
 FLAG_CAPACITY = 2
 FLAG_LAYER_OVERFLOW = 4
+FLAG_BANK_SIZE = 8
+MAX_BANK_WORDS = 8192
 
 _f = ctypes.c_float
 _P = ctypes.c_void_p
@@ -163,7 +165,7 @@ def fit_grad(det, track_hit_idx, hit_u, hit_weight, hit_lhcbid, velo_x, velo_y, 
     gq = np.zeros(n, dt)
     go = np.zeros(4 * det.n_sectors, dt)
     ds, keep = make_detector_struct(det)
-    args = [ctypes.byref(ds), ctypes.c_int64(n), _ptr(idx),
+    args = [ctypes.byref(ds), ctypes.c_int64(n), _ptr(idx), ctypes.c_int64(int(np.shape(hit_u)[0])),
             _ptr(np.ascontiguousarray(hit_u, np.float32)),
             _ptr(np.ascontiguousarray(hit_weight, np.float32)),
             _ptr(np.ascontiguousarray(hit_lhcbid, np.uint32)),

@@ -34,6 +34,7 @@ int ora_ut_decode(const ora_detector* det, const uint16_t* words, const uint32_t
     hit_offsets[b] = running;
     uint32_t start = bank_offsets[b], end = bank_offsets[b + 1];
     if (end < start) { flags |= ORA_FLAG_BANK_ORDER; continue; }
+    if (end - start > ORA_MAX_BANK_WORDS) { flags |= ORA_FLAG_BANK_SIZE; continue; }
     if (end - start > largest) largest = end - start;
     for (uint32_t i = start; i < end; ++i)
       if (words[i] & 0xFu) running++;
@@ -45,7 +46,7 @@ int ora_ut_decode(const ora_detector* det, const uint16_t* words, const uint32_t
   if (!sorted) return ORA_ERR_ARG;
   for (int64_t b = 0; b < n_banks; ++b) {
     uint32_t start = bank_offsets[b], end = bank_offsets[b + 1];
-    if (end < start) continue;
+    if (end < start || end - start > ORA_MAX_BANK_WORDS) continue;
     const int32_t l = (int32_t)((b / S) % NL);
     const int32_t s = (int32_t)(b % S);
     /* keep the valid words in bank order */
@@ -320,7 +321,7 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
  * -2 sum_{h in s} w_h r, each multiplied by grad_scale.
  * ------------------------------------------------------------------------------------------------ */
 double ora_fit_grad_f32(const ora_detector* det, int64_t n_tracks, const int32_t* track_hit_idx,
-                        const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
+                        int64_t n_hits, const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
                         const float* vx, const float* vy, const float* vtx, const float* vty,
                         const float* qop, const float* offsets, float grad_scale,
                         float* chi2_track, float* grad_qop, float* grad_offsets)
@@ -334,7 +335,8 @@ double ora_fit_grad_f32(const ora_detector* det, int64_t n_tracks, const int32_t
     float c2 = 0.0f, gq = 0.0f;
     for (int l = 0; l < NL; ++l) {
       int32_t h = track_hit_idx[t * NL + l];
-      if (h < 0) continue;
+      if (h < 0 || h >= n_hits) continue;
+      if ((hit_lhcbid[h] >> 28) >= NL || ((hit_lhcbid[h] >> 12) & 0xFFFFu) >= (uint32_t)S) continue;
       uint32_t id = hit_lhcbid[h];
       int64_t sec = (int64_t)(id >> 28) * S + ((id >> 12) & 0xFFFFu);
       /* The residual is a small difference of terms of a few hundred mm; it is evaluated in
@@ -362,7 +364,7 @@ double ora_fit_grad_f32(const ora_detector* det, int64_t n_tracks, const int32_t
 }
 
 double ora_fit_grad_f64(const ora_detector* det, int64_t n_tracks, const int32_t* track_hit_idx,
-                        const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
+                        int64_t n_hits, const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
                         const float* vx, const float* vy, const float* vtx, const float* vty,
                         const double* qop, const double* offsets, double grad_scale,
                         double* chi2_track, double* grad_qop, double* grad_offsets)
@@ -374,7 +376,8 @@ double ora_fit_grad_f64(const ora_detector* det, int64_t n_tracks, const int32_t
     double c2 = 0.0, gq = 0.0;
     for (int l = 0; l < NL; ++l) {
       int32_t h = track_hit_idx[t * NL + l];
-      if (h < 0) continue;
+      if (h < 0 || h >= n_hits) continue;
+      if ((hit_lhcbid[h] >> 28) >= NL || ((hit_lhcbid[h] >> 12) & 0xFFFFu) >= (uint32_t)S) continue;
       double dz = (double)det->z_layer[l] - (double)det->z_velo;
       double xs = (double)vx[t] + (double)vtx[t] * dz;
       double yl = (double)vy[t] + (double)vty[t] * dz;

@@ -31,6 +31,8 @@ extern "C" {
 #define ORA_FLAG_BANK_ORDER     1u  /* bank_offsets decrease: that bank is treated as empty */
 #define ORA_FLAG_CAPACITY       2u  /* more hits than hit_capacity: extra hits are not stored */
 #define ORA_FLAG_LAYER_OVERFLOW 4u  /* an (event, layer) holds >= 32768 hits: event gets no tracks */
+#define ORA_FLAG_BANK_SIZE      8u  /* a bank holds more than ORA_MAX_BANK_WORDS words: treated as empty */
+#define ORA_MAX_BANK_WORDS   8192u  /* twice the 4096 distinct 1/8-strip positions of a sector */
 #define ORA_ERR_ARG          (-1)
 
 typedef struct {
@@ -76,18 +78,19 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
                      int32_t* hit_idx, float* qop, float* chi2, int32_t* nhits,
                      int32_t* win_first, int32_t* win_size, uint8_t* active);
 
-/* Track-fit chi2 with per-sector x offsets and its adjoint in binary32.  The residual of each hit
+/* Track-fit chi2 with per-sector x offsets and its adjoint in binary32.  Hit slots with an index
+ * outside [0, n_hits) or an LHCbID naming no sector are skipped.  The residual of each hit
  * is evaluated in binary64 and rounded once to binary32; everything after that is binary32.  Any of
  * the outputs may be NULL.  Returns the total chi2 summed in double in track order. */
 double ora_fit_grad_f32(const ora_detector* det, int64_t n_tracks, const int32_t* track_hit_idx,
-                        const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
+                        int64_t n_hits, const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
                         const float* vx, const float* vy, const float* vtx, const float* vty,
                         const float* qop, const float* offsets, float grad_scale,
                         float* chi2_track, float* grad_qop, float* grad_offsets);
 
 /* The same quantities in binary64 throughout: the reference gradient. */
 double ora_fit_grad_f64(const ora_detector* det, int64_t n_tracks, const int32_t* track_hit_idx,
-                        const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
+                        int64_t n_hits, const float* hit_u, const float* hit_weight, const uint32_t* hit_lhcbid,
                         const float* vx, const float* vy, const float* vtx, const float* vty,
                         const double* qop, const double* offsets, double grad_scale,
                         double* chi2_track, double* grad_qop, double* grad_offsets);

@@ -1,0 +1,12 @@
+"""UT raw-bank decoding and Compass upstream tracking on AMD MI355X (gfx950).
+
+The computation lives in libutcompass.so (hand-written HIP, C ABI in include/ut_compass.h); this
+package is its thin ctypes binding.  See api.py.
+"""
+from .api import (Geometry, compass_params, ut_decode, compass_find, compass_fit_grad,
+                  CompassChi2Function, library, version,
+                  FLAG_BANK_ORDER, FLAG_CAPACITY, FLAG_LAYER_OVERFLOW, FLAG_BANK_SIZE, MAX_BANK_WORDS)
+
+__all__ = ["Geometry", "compass_params", "ut_decode", "compass_find", "compass_fit_grad",
+           "CompassChi2Function", "library", "version", "FLAG_BANK_ORDER", "FLAG_CAPACITY",
+           "FLAG_LAYER_OVERFLOW", "FLAG_BANK_SIZE", "MAX_BANK_WORDS"]

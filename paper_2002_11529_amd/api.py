@@ -1,0 +1,271 @@
+"""Thin ctypes binding of libutcompass.so (include/ut_compass.h).
+
+Argument marshalling only: torch provides device memory and the stream; every step of decoding,
+window search, tracklet finding, fitting and the adjoint runs in the library's HIP kernels.  The
+binding fails loudly when the library is not built or when no GPU is present; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+from .build import LIB
+
+_f = ctypes.c_float
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+
+FLAG_BANK_ORDER = 1
+FLAG_CAPACITY = 2
+FLAG_LAYER_OVERFLOW = 4
+FLAG_BANK_SIZE = 8
+MAX_BANK_WORDS = 8192
+
+
+class UtcGeometry(ctypes.Structure):
+    _fields_ = [("n_layers", _i32), ("n_sectors", _i32), ("z_layer", _f * 4), ("dxdy", _f * 4),
+                ("a_kick", _f * 4), ("z_velo", _f), ("pitch8", _f), ("u_min", _f),
+                ("sector_width", _f), ("inv_sector_width", _f), ("y_begin", _f), ("y_end", _f),
+                ("weight_by_size", _f * 16), ("u0", _P)]
+
+
+class UtcCompassParams(ctypes.Structure):
+    _fields_ = [("w0", _f), ("kw", _f), ("p_min", _f), ("max_hits", _i32),
+                ("n_sectors_search", _i32), ("slope_tol", _f), ("completion_tol", _f)]
+
+
+class UtcLaunchConfig(ctypes.Structure):
+    _fields_ = [("block", _i32), ("grid", _i32), ("reserved0", _i32), ("reserved1", _i32)]
+
+
+_lib = None
+
+
+def library():
+    """Load libutcompass.so (built in-tree by paper_2002_11529_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise RuntimeError(f"{LIB} is not built; run `python -m paper_2002_11529_amd.build`")
+    L = ctypes.CDLL(LIB)
+    L.ut_decode_workspace_bytes.restype = _sz
+    L.ut_decode_workspace_bytes.argtypes = [_i32, _i32]
+    L.ut_decode.restype = ctypes.c_int
+    L.ut_decode.argtypes = [_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P]
+    L.compass_find_workspace_bytes.restype = _sz
+    L.compass_find_workspace_bytes.argtypes = [_i32, _i64]
+    L.compass_find.restype = ctypes.c_int
+    L.compass_find.argtypes = [_P, _P, _i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _i64,
+                               _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P]
+    L.compass_fit_grad_workspace_bytes.restype = _sz
+    L.compass_fit_grad_workspace_bytes.argtypes = [_i32]
+    L.compass_fit_grad.restype = ctypes.c_int
+    L.compass_fit_grad.argtypes = [_P, _i64, _P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _f, _P,
+                                   _P, _P, _P, _P, _sz, _P]
+    L.utc_status_string.restype = ctypes.c_char_p
+    L.utc_status_string.argtypes = [ctypes.c_int]
+    L.utc_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = library().utc_status_string(status).decode()
+        raise RuntimeError(f"{what} failed: {msg} ({status})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    c = UtcLaunchConfig()
+    c.block = int(launch.get("block", 256))
+    c.grid = int(launch.get("grid", 0))
+    return ctypes.byref(c)
+
+
+class Geometry:
+    """Detector description for the library: float32 scalars plus the device u0 table."""
+
+    def __init__(self, det, device="cuda"):
+        self.n_sectors = int(det.n_sectors)
+        self.u0 = torch.as_tensor(det.u0, dtype=torch.float32).to(device).contiguous()
+        s = UtcGeometry()
+        s.n_layers = 4
+        s.n_sectors = self.n_sectors
+        for i in range(4):
+            s.z_layer[i] = float(det.z_layer[i])
+            s.dxdy[i] = float(det.dxdy[i])
+            s.a_kick[i] = float(det.a_kick[i])
+        s.z_velo = float(det.z_velo)
+        s.pitch8 = float(det.pitch8)
+        s.u_min = float(det.u_min)
+        s.sector_width = float(det.sector_width)
+        s.inv_sector_width = float(det.inv_sector_width)
+        s.y_begin = float(det.y_begin)
+        s.y_end = float(det.y_end)
+        for i in range(16):
+            s.weight_by_size[i] = float(det.weight_by_size[i])
+        s.u0 = self.u0.data_ptr()
+        self.struct = s
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.struct)
+
+
+def compass_params(p) -> UtcCompassParams:
+    s = UtcCompassParams()
+    s.w0, s.kw, s.p_min = float(p.w0), float(p.kw), float(p.p_min)
+    s.max_hits, s.n_sectors_search = int(p.max_hits), int(p.n_sectors_search)
+    s.slope_tol, s.completion_tol = float(p.slope_tol), float(p.completion_tol)
+    return s
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def ut_decode(geom: Geometry, words, bank_offsets, n_events: int, hit_capacity: Optional[int] = None,
+              error_flags=None, launch=None, out=None, workspace=None, stream=None):
+    """Decode raw banks into the hit structure of arrays.  Returns a dict of device tensors."""
+    L = library()
+    dev = words.device
+    n_banks = n_events * 4 * geom.n_sectors
+    if bank_offsets.shape[0] != n_banks + 1:
+        raise ValueError("bank_offsets must have n_events*4*S + 1 entries")
+    cap = int(words.shape[0]) if hit_capacity is None else int(hit_capacity)
+    if out is None:
+        out = dict(hit_offsets=torch.empty(n_banks + 1, dtype=torch.int32, device=dev),
+                   lhcbid=torch.empty(cap, dtype=torch.int32, device=dev),
+                   z=torch.empty(cap, dtype=torch.float32, device=dev),
+                   u=torch.empty(cap, dtype=torch.float32, device=dev),
+                   y_begin=torch.empty(cap, dtype=torch.float32, device=dev),
+                   y_end=torch.empty(cap, dtype=torch.float32, device=dev),
+                   weight=torch.empty(cap, dtype=torch.float32, device=dev))
+    if error_flags is None:
+        error_flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    out["error_flags"] = error_flags
+    if workspace is None:
+        workspace = _workspace(L.ut_decode_workspace_bytes(n_events, geom.n_sectors), dev)
+    st = L.ut_decode(geom.ref, _ptr(words), _ptr(bank_offsets), n_events, cap,
+                     _ptr(out["hit_offsets"]), _ptr(out["lhcbid"]), _ptr(out["z"]), _ptr(out["u"]),
+                     _ptr(out["y_begin"]), _ptr(out["y_end"]), _ptr(out["weight"]),
+                     _ptr(error_flags), _ptr(workspace), workspace.numel(), _launch(launch),
+                     _stream(stream))
+    _check(st, "ut_decode")
+    return out
+
+
+def compass_find(geom: Geometry, params, n_events: int, hits, vx, vy, vtx, vty, velo_offsets,
+                 windows: bool = False, error_flags=None, launch=None, out=None, workspace=None,
+                 stream=None):
+    """Compass tracklet search for every VELO track.  Returns a dict of device tensors."""
+    L = library()
+    dev = vx.device
+    n = int(vx.shape[0])
+    if out is None:
+        out = dict(hit_idx=torch.empty((n, 4), dtype=torch.int32, device=dev),
+                   qop=torch.empty(n, dtype=torch.float32, device=dev),
+                   chi2=torch.empty(n, dtype=torch.float32, device=dev),
+                   nhits=torch.empty(n, dtype=torch.int32, device=dev))
+        if windows:
+            out["windows"] = torch.empty((n, 4, 2), dtype=torch.int16, device=dev)
+    if error_flags is None:
+        error_flags = hits.get("error_flags") if isinstance(hits, dict) else None
+        if error_flags is None:
+            error_flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    out["error_flags"] = error_flags
+    if workspace is None:
+        workspace = _workspace(L.compass_find_workspace_bytes(n_events, n), dev)
+    p = params if isinstance(params, UtcCompassParams) else compass_params(params)
+    st = L.compass_find(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"]),
+                        _ptr(hits["u"]), _ptr(hits["weight"]), _ptr(hits["y_begin"]),
+                        _ptr(hits["y_end"]), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty),
+                        _ptr(velo_offsets), n, _ptr(out["hit_idx"]), _ptr(out["qop"]),
+                        _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out.get("windows")),
+                        _ptr(error_flags), _ptr(workspace), workspace.numel(), _launch(launch),
+                        _stream(stream))
+    _check(st, "compass_find")
+    return out
+
+
+def compass_fit_grad(geom: Geometry, track_hit_idx, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty,
+                     qop, offsets, grad_scale: float = 1.0, want_grad: bool = True,
+                     want_chi2_track: bool = True, out=None, workspace=None, stream=None):
+    """Chi2 of the frozen track fits and (optionally) its gradients.  Returns a dict of tensors."""
+    L = library()
+    dev = qop.device
+    n = int(qop.shape[0])
+    S = geom.n_sectors
+    if out is None:
+        out = dict(chi2_total=torch.empty(1, dtype=torch.float64, device=dev))
+        if want_chi2_track:
+            out["chi2_track"] = torch.empty(n, dtype=torch.float32, device=dev)
+        if want_grad:
+            out["grad_qop"] = torch.empty(n, dtype=torch.float32, device=dev)
+            out["grad_offsets"] = torch.empty(4 * S, dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = _workspace(L.compass_fit_grad_workspace_bytes(S), dev)
+    st = L.compass_fit_grad(geom.ref, n, _ptr(track_hit_idx), int(hit_u.shape[0]), _ptr(hit_u),
+                            _ptr(hit_weight),
+                            _ptr(hit_lhcbid), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty), _ptr(qop),
+                            _ptr(offsets), float(grad_scale), _ptr(out.get("chi2_track")),
+                            _ptr(out.get("chi2_total")), _ptr(out.get("grad_qop")),
+                            _ptr(out.get("grad_offsets")), _ptr(workspace), workspace.numel(),
+                            _stream(stream))
+    _check(st, "compass_fit_grad")
+    return out
+
+
+class CompassChi2Function(torch.autograd.Function):
+    """chi2_total(qop, offsets) of frozen track fits, with the library's hand-written adjoint.
+
+    Usage: chi2 = CompassChi2Function.apply(qop, offsets, geom, frozen) where `frozen` is a dict of
+    device tensors track_hit_idx, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty.
+    """
+
+    @staticmethod
+    def forward(ctx, qop, offsets, geom, frozen):
+        r = compass_fit_grad(geom, frozen["track_hit_idx"], frozen["hit_u"], frozen["hit_weight"],
+                             frozen["hit_lhcbid"], frozen["vx"], frozen["vy"], frozen["vtx"],
+                             frozen["vty"], qop.detach().contiguous(), offsets.detach().contiguous(),
+                             want_grad=False, want_chi2_track=False)
+        ctx.save_for_backward(qop, offsets)
+        ctx.geom, ctx.frozen = geom, frozen
+        return r["chi2_total"][0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        qop, offsets = ctx.saved_tensors
+        f = ctx.frozen
+        r = compass_fit_grad(ctx.geom, f["track_hit_idx"], f["hit_u"], f["hit_weight"],
+                             f["hit_lhcbid"], f["vx"], f["vy"], f["vtx"], f["vty"],
+                             qop.detach().contiguous(), offsets.detach().contiguous(),
+                             grad_scale=1.0, want_grad=True, want_chi2_track=False)
+        g = grad_out.to(torch.float32)
+        return r["grad_qop"] * g, r["grad_offsets"] * g, None, None
+
+
+def version() -> str:
+    return library().utc_version().decode()

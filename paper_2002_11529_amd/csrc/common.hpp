@@ -1,0 +1,98 @@
+// Device-side helpers shared by the kernels of libutcompass (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ut_compass.h"
+
+namespace utc {
+
+constexpr int kLayers = 4;
+constexpr int kWave = 64;
+
+// Geometry as a by-value kernel argument (the device table u0 stays a pointer).
+struct Geom {
+  int32_t S;
+  float z_layer[4];
+  float dxdy[4];
+  float a_kick[4];
+  float z_velo;
+  float pitch8;
+  float u_min;
+  float sector_width;
+  float inv_sector_width;
+  float y_begin, y_end;
+  float weight_by_size[16];
+  const float* u0;
+};
+
+inline Geom make_geom(const utc_geometry& g) {
+  Geom d;
+  d.S = g.n_sectors;
+  for (int l = 0; l < 4; ++l) {
+    d.z_layer[l] = g.z_layer[l];
+    d.dxdy[l] = g.dxdy[l];
+    d.a_kick[l] = g.a_kick[l];
+  }
+  d.z_velo = g.z_velo;
+  d.pitch8 = g.pitch8;
+  d.u_min = g.u_min;
+  d.sector_width = g.sector_width;
+  d.inv_sector_width = g.inv_sector_width;
+  d.y_begin = g.y_begin;
+  d.y_end = g.y_end;
+  for (int i = 0; i < 16; ++i) d.weight_by_size[i] = g.weight_by_size[i];
+  d.u0 = g.u0;
+  return d;
+}
+
+__device__ inline void raise_flag(uint32_t* flags, uint32_t bit) {
+  if (flags) atomicOr(flags, bit);
+}
+
+// Inclusive scan across one wavefront.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ inline uint32_t wave_sum(uint32_t x) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// Exclusive scan across the workgroup.  `tmp` holds blockDim.x/64 + 1 words of LDS.  All threads
+// must call it; it ends with a barrier so `tmp` may be reused right after.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  uint32_t x = wave_inclusive_scan(v);
+  if (lane == kWave - 1) tmp[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t t = lane < nw ? tmp[lane] : 0u;
+    t = wave_inclusive_scan(t);
+    if (lane < nw) tmp[lane] = t;
+  }
+  __syncthreads();
+  uint32_t before = wid > 0 ? tmp[wid - 1] : 0u;
+  *total = tmp[nw - 1];
+  __syncthreads();
+  return before + x - v;
+}
+
+__device__ inline uint32_t block_sum(uint32_t v, uint32_t* tmp) {
+  uint32_t total;
+  block_exclusive_scan(v, tmp, &total);
+  return total;
+}
+
+}  // namespace utc

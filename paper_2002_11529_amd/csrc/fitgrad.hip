@@ -1,0 +1,176 @@
+// Track-fit chi2 with per-sector alignment offsets and its hand-written adjoint, for gfx950.
+//
+// The fit of the tracklet search (Sections III-C and V-B) with the hit assignment frozen, seen as a
+// function of the per-sector x offsets delta and the per-track q/p.  One thread per track computes
+// its chi2 and d chi2/d qop directly; the per-sector sums of w*r and the total chi2 are accumulated
+// exactly as integers in units of 2^-40 (a hi/lo pair of 64-bit words per sum), first in LDS per
+// workgroup and then with one global atomic per workgroup and sector, so the result is the same
+// for every schedule and launch shape.
+#include "common.hpp"
+
+namespace utc {
+
+constexpr double kFix = 1099511627776.0;           // 2^40
+constexpr double kTwo32 = 4294967296.0;            // 2^32
+constexpr int kMaxLdsSectors = 4 * 1024;           // 4*S sums held in LDS (16 B each)
+
+// Split x * 2^40 into hi * 2^32 + lo with 0 <= lo < 2^32 (lo rounded to an integer).
+__device__ inline void to_fixed(double x, uint64_t& hi_out, uint64_t& lo_out) {
+  const double c = x * kFix;
+  double hi = floor(c * (1.0 / kTwo32));
+  double lo = rint(c - hi * kTwo32);
+  if (lo >= kTwo32) { lo -= kTwo32; hi += 1.0; }
+  hi_out = (uint64_t)(int64_t)hi;
+  lo_out = (uint64_t)lo;
+}
+
+__device__ inline double from_fixed(uint64_t hi, uint64_t lo) {
+  return ((double)(int64_t)hi * kTwo32 + (double)lo) / kFix;
+}
+
+// acc layout: [2*k] = hi, [2*k+1] = lo for k in 0 .. 4S (index 4S is the total chi2)
+__global__ void k_fitgrad_clear(uint64_t* acc, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc[i] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, int64_t n_hits,
+          const float* __restrict__ hu, const float* __restrict__ hw,
+          const uint32_t* __restrict__ hid, const float* __restrict__ vx,
+          const float* __restrict__ vy, const float* __restrict__ vtx,
+          const float* __restrict__ vty, const float* __restrict__ qop,
+          const float* __restrict__ offsets, float m2s, float* __restrict__ chi2_track,
+          float* __restrict__ grad_qop, bool want_offsets, bool want_total, bool lds,
+          uint64_t* acc)
+{
+  extern __shared__ uint64_t s_acc[];  // [2 * (4S + 1)] when `lds`
+  const int S = g.S;
+  const int n_sums = kLayers * S + 1;
+  if (lds) {
+    for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x) s_acc[i] = 0;
+    __syncthreads();
+  }
+  uint64_t* sums = lds ? s_acc : acc;
+  double dz[kLayers];
+#pragma unroll
+  for (int l = 0; l < kLayers; ++l) dz[l] = (double)g.z_layer[l] - (double)g.z_velo;
+
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tracks;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double x0 = vx[t], y0 = vy[t], tx = vtx[t], ty = vty[t];
+    const double q = qop[t];
+    float c2 = 0.0f, gq = 0.0f;
+#pragma unroll
+    for (int l = 0; l < kLayers; ++l) {
+      const int32_t h = track_hit_idx[t * kLayers + l];
+      if (h < 0 || h >= n_hits) continue;
+      const uint32_t id = hid[h];
+      if ((id >> 28) >= (uint32_t)kLayers || ((id >> 12) & 0xFFFFu) >= (uint32_t)S) continue;
+      const int sec = (int)(id >> 28) * S + (int)((id >> 12) & 0xFFFFu);
+      const double xs = x0 + tx * dz[l];
+      const double yl = y0 + ty * dz[l];
+      const double m = (double)hu[h] + yl * (double)g.dxdy[l];
+      const float r = (float)(((m - (double)offsets[sec]) - xs) - (double)g.a_kick[l] * q);
+      const float wr = hw[h] * r;
+      c2 = c2 + wr * r;
+      gq = gq + wr * g.a_kick[l];
+      if (want_offsets) {
+        uint64_t hi, lo;
+        to_fixed((double)wr, hi, lo);
+        atomicAdd((unsigned long long*)&sums[2 * sec], (unsigned long long)hi);
+        atomicAdd((unsigned long long*)&sums[2 * sec + 1], (unsigned long long)lo);
+      }
+    }
+    if (chi2_track) chi2_track[t] = c2;
+    if (grad_qop) grad_qop[t] = m2s * gq;
+    if (want_total) {
+      uint64_t hi, lo;
+      to_fixed((double)c2, hi, lo);
+      atomicAdd((unsigned long long*)&sums[2 * (n_sums - 1)], (unsigned long long)hi);
+      atomicAdd((unsigned long long*)&sums[2 * (n_sums - 1) + 1], (unsigned long long)lo);
+    }
+  }
+  if (lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x) {
+      const uint64_t v = s_acc[i];
+      if (v) atomicAdd((unsigned long long*)&acc[i], (unsigned long long)v);
+    }
+  }
+}
+
+__global__ void k_fitgrad_finalize(const uint64_t* __restrict__ acc, int n_sums, double scale2,
+                                   float* __restrict__ grad_offsets, double* __restrict__ chi2_total)
+{
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sums; i += gridDim.x * blockDim.x) {
+    const double v = from_fixed(acc[2 * i], acc[2 * i + 1]);
+    if (i == n_sums - 1) {
+      if (chi2_total) *chi2_total = v;
+    } else if (grad_offsets) {
+      grad_offsets[i] = (float)(scale2 * v);
+    }
+  }
+}
+
+}  // namespace utc
+
+using namespace utc;
+
+extern "C" size_t compass_fit_grad_workspace_bytes(int32_t n_sectors)
+{
+  if (n_sectors < 1) return 0;
+  const size_t n = 2 * ((size_t)kLayers * n_sectors + 1) * sizeof(uint64_t);
+  return (n + 255) / 256 * 256;
+}
+
+extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks,
+                                       const int32_t* track_hit_idx, int64_t n_hits,
+                                       const float* hit_u,
+                                       const float* hit_weight, const uint32_t* hit_lhcbid,
+                                       const float* vx, const float* vy, const float* vtx,
+                                       const float* vty, const float* qop, const float* offsets,
+                                       float grad_scale, float* chi2_track, double* chi2_total,
+                                       float* grad_qop, float* grad_offsets, void* workspace,
+                                       size_t workspace_bytes, hipStream_t stream)
+{
+  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
+      n_tracks < 0 || n_hits < 0)
+    return UTC_ERR_ARG;
+  if (n_tracks > 0 && (!track_hit_idx || !hit_u || !hit_weight || !hit_lhcbid || !vx || !vy ||
+                       !vtx || !vty || !qop || !offsets))
+    return UTC_ERR_ARG;
+  if (!workspace || workspace_bytes < compass_fit_grad_workspace_bytes(geom->n_sectors))
+    return UTC_ERR_WORKSPACE;
+  const Geom g = make_geom(*geom);
+  const int S = geom->n_sectors;
+  const int n_sums = kLayers * S + 1;
+  uint64_t* acc = static_cast<uint64_t*>(workspace);
+  const bool want_offsets = grad_offsets != nullptr;
+  const bool want_total = chi2_total != nullptr;
+  const float m2s = -2.0f * grad_scale;
+  if (want_offsets || want_total)
+    hipLaunchKernelGGL(k_fitgrad_clear, dim3((2 * n_sums + 255) / 256), dim3(256), 0, stream, acc,
+                       2 * n_sums);
+  if (n_tracks > 0) {
+    const int block = 256;
+    int64_t blocks = (n_tracks + block - 1) / block;
+    if (blocks > 2048) blocks = 2048;
+    const bool use_lds = (want_offsets || want_total) && n_sums <= kMaxLdsSectors + 1;
+    const size_t lds = use_lds ? 2 * (size_t)n_sums * sizeof(uint64_t) : 0;
+    if (lds > 64 * 1024) {
+      static bool attr_set = false;
+      if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fitgrad),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+      }
+    }
+    hipLaunchKernelGGL(k_fitgrad, dim3((unsigned)blocks), dim3(block), lds, stream, g, n_tracks,
+                       track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop, offsets,
+                       m2s, chi2_track, grad_qop, want_offsets, want_total, use_lds, acc);
+  }
+  if (want_offsets || want_total)
+    hipLaunchKernelGGL(k_fitgrad_finalize, dim3((n_sums + 255) / 256), dim3(256), 0, stream, acc,
+                       n_sums, -2.0 * (double)grad_scale, grad_offsets, chi2_total);
+  return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
+}

@@ -1,0 +1,79 @@
+"""Helpers of the GPU tests: run the HIP path and the oracle on the same seeded batch."""
+import numpy as np
+import torch
+
+import oracle
+import paper_2002_11529_amd as utc
+
+DEV = torch.device("cuda:0")
+
+
+def to_dev(b):
+    return dict(
+        words=torch.from_numpy(b.words.view(np.int16).copy()).to(DEV),
+        bank_offsets=torch.from_numpy(b.bank_offsets.view(np.int32).copy()).to(DEV),
+        vel=[torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+             for a in (b.velo_x, b.velo_y, b.velo_tx, b.velo_ty)],
+        velo_offsets=torch.from_numpy(b.velo_offsets.view(np.int32).copy()).to(DEV))
+
+
+def gpu_run(b, launch_decode=None, launch_find=None, windows=True, hit_capacity=None, find=True):
+    dv = to_dev(b)
+    geom = utc.Geometry(b.detector, DEV)
+    hits = utc.ut_decode(geom, dv["words"], dv["bank_offsets"], b.n_events, hit_capacity=hit_capacity,
+                         launch=launch_decode)
+    res = {}
+    if find:
+        res = utc.compass_find(geom, b.params, b.n_events, hits, *dv["vel"], dv["velo_offsets"],
+                               windows=windows, launch=launch_find)
+    torch.cuda.synchronize()
+    h = {k: v.cpu().numpy() for k, v in hits.items()}
+    h["hit_offsets"] = h["hit_offsets"].view(np.uint32)
+    h["lhcbid"] = h["lhcbid"].view(np.uint32)
+    h["error_flags"] = int(h["error_flags"].view(np.uint32)[0])
+    r = {k: v.cpu().numpy() for k, v in res.items()}
+    if find:
+        r["error_flags"] = int(r["error_flags"].view(np.uint32)[0])
+    return h, r, geom, hits, res, dv
+
+
+def oracle_run(b, hit_capacity=None, find=True):
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events, hit_capacity=hit_capacity)
+    c = None
+    if find:
+        c = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx,
+                           b.velo_ty, b.velo_offsets, with_windows=True)
+    return d, c
+
+
+def assert_decode_equal(h, d):
+    n = int(d["hit_offsets"][-1])
+    assert np.array_equal(h["hit_offsets"], d["hit_offsets"])
+    for k in ("lhcbid", "z", "u", "y_begin", "y_end", "weight"):
+        a, e = h[k][:n], d[k][:n]
+        bad = np.nonzero(a.view(np.uint32) != e.view(np.uint32))[0]
+        assert bad.size == 0, f"{k}: {bad.size} mismatches, first at {bad[:5]}"
+
+
+def oracle_windows_rel(b, d, c):
+    """Oracle windows as (first - first hit of the (event, layer), size), (-1, 0) if not searched."""
+    S = b.detector.n_sectors
+    ev = np.repeat(np.arange(b.n_events), np.diff(b.velo_offsets.astype(np.int64)))
+    out = np.zeros((b.n_tracks, 4, 2), np.int64)
+    for l in range(4):
+        layer_first = d["hit_offsets"][(ev * 4 + l) * S].astype(np.int64)
+        act = c["active"].astype(bool)
+        out[:, l, 0] = np.where(act, c["win_first"][:, l] - layer_first, -1)
+        out[:, l, 1] = c["win_size"][:, l]
+    return out
+
+
+def assert_compass_equal(r, c, b=None, d=None):
+    assert np.array_equal(r["nhits"], c["nhits"]), np.nonzero(r["nhits"] != c["nhits"])[0][:10]
+    bad = np.nonzero((r["hit_idx"] != c["hit_idx"]).any(axis=1))[0]
+    assert bad.size == 0, f"hit_idx differs for {bad.size} tracks, first {bad[:10]}"
+    assert np.array_equal(r["qop"].view(np.uint32), c["qop"].view(np.uint32))
+    assert np.array_equal(r["chi2"].view(np.uint32), c["chi2"].view(np.uint32))
+    if b is not None and "windows" in r:
+        w = oracle_windows_rel(b, d, c)
+        assert np.array_equal(r["windows"].astype(np.int64), w)
