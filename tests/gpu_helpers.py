@@ -38,7 +38,9 @@ def gpu_run(b, launch_decode=None, launch_find=None, windows=True, hit_capacity=
 
 
 def oracle_run(b, hit_capacity=None, find=True):
-    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events, hit_capacity=hit_capacity)
+    # same default capacity as the GPU call: one slot per raw word
+    cap = b.n_words if hit_capacity is None else hit_capacity
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events, hit_capacity=cap)
     c = None
     if find:
         c = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx,

@@ -76,8 +76,10 @@ def test_decode_launch_shapes_agree(launch):
     h0, r0, *_ = gpu_run(b)
     h1, r1, *_ = gpu_run(b, launch_decode=launch,
                          launch_find=dict(block=min(launch["block"], 256), grid=launch.get("grid", 0)))
-    for k in ("hit_offsets", "lhcbid", "u", "weight"):
-        assert np.array_equal(h0[k], h1[k])
+    n = int(h0["hit_offsets"][-1])
+    assert np.array_equal(h0["hit_offsets"], h1["hit_offsets"])
+    for k in ("lhcbid", "u", "weight"):
+        assert np.array_equal(h0[k][:n], h1[k][:n])
     for k in ("hit_idx", "nhits", "qop", "chi2", "windows"):
         assert np.array_equal(r0[k], r1[k])
 
