@@ -47,6 +47,16 @@ inline Geom make_geom(const utc_geometry& g) {
   return d;
 }
 
+// Allow `bytes` of dynamic LDS for `func` (needed above 64 KiB).  Clears the error state on failure.
+inline bool allow_dynamic_lds(const void* func, size_t bytes) {
+  if (bytes <= 64 * 1024) return true;
+  if (hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
 __device__ inline void raise_flag(uint32_t* flags, uint32_t bit) {
   if (flags) atomicOr(flags, bit);
 }
@@ -93,6 +103,57 @@ __device__ inline uint32_t block_sum(uint32_t v, uint32_t* tmp) {
   uint32_t total;
   block_exclusive_scan(v, tmp, &total);
   return total;
+}
+
+}  // namespace utc
+
+namespace utc {
+
+// ---- wavefront helpers (wave64) ----
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Orders the LDS accesses of one wavefront: the compiler may not move memory operations across it
+// and earlier LDS writes of any lane are visible to later reads of any lane of the same wave.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ inline uint32_t lanes_before(uint64_t mask) {
+  return (uint32_t)__popcll(mask & __lanemask_lt());
+}
+
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+template <class T>
+__device__ inline T wave_bcast(T v, int src) { return __shfl(v, src, kWave); }
+
+__device__ inline uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
+  const uint32_t inc = wave_inclusive_scan(x);
+  *total = __shfl(inc, kWave - 1, kWave);
+  return inc - x;
+}
+
+// First index i in [lo, hi) with pred(i) true for a predicate that is false then true.
+template <class P>
+__device__ inline int64_t first_true(int64_t lo, int64_t hi, P pred) {
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (pred(mid)) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// The same over 32-bit indices.
+template <class P>
+__device__ inline uint32_t first_true_u32(uint32_t lo, uint32_t hi, P pred) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (pred(mid)) hi = mid; else lo = mid + 1;
+  }
+  return lo;
 }
 
 }  // namespace utc

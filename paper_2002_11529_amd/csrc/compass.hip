@@ -1,243 +1,95 @@
-// Compass tracking (Section V of the paper) for gfx950.
+// Compass tracking (Section V of the paper) for gfx950: stand-alone kernel over decoded hits.
 //
-// For every VELO track: straight-line extrapolation to the four layers, acceptance filter, hit
-// windows (binary searches over the x-sorted hits of the central sector and its neighbours, cut to
-// the max_hits hits nearest to the prediction), then the tracklet search: anchor pairs in the first
-// and third panel (forward) or fourth and second (backward), slope test against the VELO slope,
-// completion hits in the other two panels inside the interval spanned by the pair-slope and
-// VELO-slope extrapolations, one-parameter chi2 fit in q/p for each candidate, and selection under
-// a total order (more hits, lower chi2, smaller hit indices).
-#include "common.hpp"
+// One workgroup per event at a time (events strided over the grid): the event's bank offsets and, when
+// they fit, the u of its hits are staged in LDS; then each wavefront runs the search for groups of
+// 16 VELO tracks (compass_group.hpp): windows by binary search over the staged hits, tracklets by
+// anchor pairs spread over the lanes, selection by an LDS atomic minimum of a total-order key.
+#include "compass_group.hpp"
 
 namespace utc {
 
-struct CPar {
-  float W;            // window half-width (mm)
-  int max_hits;       // per-layer window cap
-  int half;           // (n_sectors_search - 1) / 2
-  float slope_tol;
-  float eps;          // completion interval margin (mm)
-};
-
-// anchor A, anchor B, completion C1, completion C2 for the forward and backward directions
-__constant__ int kDirs[2][4] = {{0, 2, 1, 3}, {3, 1, 2, 0}};
-
-// First index i in [lo, hi) with pred(i) true for a predicate that is false then true.
-template <class P>
-__device__ inline int64_t first_true(int64_t lo, int64_t hi, P pred) {
-  while (lo < hi) {
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (pred(mid)) hi = mid; else lo = mid + 1;
-  }
-  return lo;
-}
-
-struct Best {
-  int n;          // 0 = none
-  float q, chi2;
-  int32_t idx[kLayers];
-};
-
-__device__ inline bool better(int n, float chi2, const int32_t idx[kLayers], const Best& b) {
-  if (b.n == 0) return true;
-  if (n != b.n) return n > b.n;
-  if (chi2 < b.chi2) return true;
-  if (chi2 > b.chi2) return false;
-#pragma unroll
-  for (int l = 0; l < kLayers; ++l)
-    if (idx[l] != b.idx[l]) return idx[l] < b.idx[l];
-  return false;
-}
-
-__device__ inline void fit(const Geom& g, const float xs[kLayers], const float yl[kLayers],
-                           const float* __restrict__ hu, const float* __restrict__ hw,
-                           const int32_t idx[kLayers], float& q_out, float& chi2_out) {
-  float r[kLayers];
-  float Sar = 0.0f, Saa = 0.0f;
-#pragma unroll
-  for (int l = 0; l < kLayers; ++l) {
-    if (idx[l] < 0) continue;
-    const float m = hu[idx[l]] + yl[l] * g.dxdy[l];
-    r[l] = m - xs[l];
-    const float wa = hw[idx[l]] * g.a_kick[l];
-    Sar = Sar + wa * r[l];
-    Saa = Saa + wa * g.a_kick[l];
-  }
-  const float q = Sar / Saa;
-  float chi2 = 0.0f;
-#pragma unroll
-  for (int l = 0; l < kLayers; ++l) {
-    if (idx[l] < 0) continue;
-    const float e = r[l] - g.a_kick[l] * q;
-    chi2 = chi2 + (hw[idx[l]] * e) * e;
-  }
-  q_out = q;
-  chi2_out = chi2;
-}
-
-__device__ inline bool y_ok(const float* __restrict__ yb, const float* __restrict__ ye, int64_t i, float y) {
-  return yb[i] <= y && y <= ye[i];
-}
-
-// One thread processes one VELO track.
 __global__ void __launch_bounds__(256)
-k_compass_thread(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
-                 const float* __restrict__ hu, const float* __restrict__ hw,
-                 const float* __restrict__ hyb, const float* __restrict__ hye,
-                 const float* __restrict__ vx, const float* __restrict__ vy,
-                 const float* __restrict__ vtx, const float* __restrict__ vty,
-                 const uint32_t* __restrict__ velo_offsets, int32_t* __restrict__ hit_idx,
-                 float* __restrict__ qop, float* __restrict__ chi2, int32_t* __restrict__ nhits,
-                 int16_t* __restrict__ windows, uint32_t* flags)
+k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
+          const float* __restrict__ hu, const float* __restrict__ hw,
+          const float* __restrict__ hyb, const float* __restrict__ hye,
+          const uint32_t* __restrict__ velo_offsets, TrackIO io, uint32_t* flags, int u_cap)
 {
+  extern __shared__ __align__(16) char smem[];
   const int S = g.S;
-  const float u_max = g.u_min + (float)S * g.sector_width;
+  const int nb = kLayers * S;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int wid = tid / kWave, nwaves = bs / kWave;
+  uint32_t* s_hoff = reinterpret_cast<uint32_t*>(smem);
+  float* s_u = reinterpret_cast<float*>(s_hoff + ((nb + 1 + 3) & ~3));
+  char* gbase = reinterpret_cast<char*>(s_u + u_cap);
+  const GroupScratch gs = carve_group(gbase + (size_t)wid * group_scratch_bytes(p.max_hits), p.max_hits);
+
   for (int e = blockIdx.x; e < n_events; e += gridDim.x) {
-    int64_t layer_first[kLayers];
+    const int64_t eb = (int64_t)e * nb;
+    const uint32_t H = hit_offsets[eb];
+    for (int j0 = 0; j0 <= nb; j0 += 4 * bs) {
+      uint32_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q * bs + tid;
+        v[q] = j <= nb ? hit_offsets[eb + j] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q * bs + tid;
+        if (j <= nb) s_hoff[j] = v[q] - H;
+      }
+    }
+    __syncthreads();
+    const uint32_t nh = s_hoff[nb];
     bool overflow = false;
 #pragma unroll
-    for (int l = 0; l < kLayers; ++l) {
-      const int64_t b0 = ((int64_t)e * kLayers + l) * S;
-      layer_first[l] = hit_offsets[b0];
-      if ((int64_t)hit_offsets[b0 + S] - layer_first[l] > 32767) overflow = true;
-    }
-    if (overflow && threadIdx.x == 0) raise_flag(flags, UTC_FLAG_LAYER_OVERFLOW);
-    const uint32_t t1 = velo_offsets[e + 1];
-    for (uint32_t t = velo_offsets[e] + threadIdx.x; t < t1; t += blockDim.x) {
-      const float x0 = vx[t], y0 = vy[t], tx = vtx[t], ty = vty[t];
-      float xs[kLayers], yl[kLayers], up[kLayers];
+    for (int l = 0; l < kLayers; ++l)
+      if (s_hoff[(l + 1) * S] - s_hoff[l * S] > 32767u) overflow = true;
+    const bool staged = nh <= (uint32_t)u_cap;
+    if (staged) {
+      for (uint32_t k0 = 0; k0 < nh; k0 += 8 * bs) {
+        float v[8];
 #pragma unroll
-      for (int l = 0; l < kLayers; ++l) {
-        const float dz = g.z_layer[l] - g.z_velo;
-        xs[l] = x0 + tx * dz;
-        yl[l] = y0 + ty * dz;
-        up[l] = xs[l] - yl[l] * g.dxdy[l];
-      }
-      bool active = !overflow;
-      if (active) {
-        const int chk[2] = {0, kLayers - 1};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int l = chk[k];
-          if (!(g.y_begin <= yl[l] && yl[l] <= g.y_end)) active = false;
-          if (!(g.u_min <= up[l] && up[l] <= u_max)) active = false;
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t k = k0 + q * bs + tid;
+          v[q] = k < nh ? hu[(int64_t)H + k] : 0.0f;
         }
-      }
-      int64_t wf[kLayers];
-      int wn[kLayers];
-      Best best;
-      best.n = 0;
-      best.q = 0.0f;
-      best.chi2 = 0.0f;
 #pragma unroll
-      for (int l = 0; l < kLayers; ++l) { best.idx[l] = -1; wf[l] = -1; wn[l] = 0; }
-
-      if (active) {
-        // windows (Section V-A)
-#pragma unroll
-        for (int l = 0; l < kLayers; ++l) {
-          const float ts = floorf((up[l] - g.u_min) * g.inv_sector_width);
-          const int c = ts < 0.0f ? 0 : (ts > (float)(S - 1) ? S - 1 : (int)ts);
-          const int s_lo = c - p.half < 0 ? 0 : c - p.half;
-          const int s_hi = c + p.half > S - 1 ? S - 1 : c + p.half;
-          const int64_t b0 = ((int64_t)e * kLayers + l) * S;
-          const int64_t H0 = hit_offsets[b0 + s_lo], H1 = hit_offsets[b0 + s_hi + 1];
-          const float lo = up[l] - p.W, hi = up[l] + p.W;
-          const float upl = up[l];
-          int64_t first = first_true(H0, H1, [&](int64_t i) { return hu[i] >= lo; });
-          int64_t end = first_true(first, H1, [&](int64_t i) { return hu[i] > hi; });
-          const int N = p.max_hits;
-          if (end - first > N) {
-            // the N nearest: first start f whose left hit is no farther than the hit just past
-            // the window; equals dropping the farther end one at a time, the right one on ties
-            const int64_t a = first_true(first, end - N, [&](int64_t f) {
-              return (upl - hu[f]) <= (hu[f + N] - upl);
-            });
-            first = a;
-            end = a + N;
-          }
-          wf[l] = first;
-          wn[l] = (int)(end - first);
-        }
-
-        // tracklet search (Section V-B)
-        for (int dir = 0; dir < 2 && best.n == 0; ++dir) {
-          const int A = kDirs[dir][0], B = kDirs[dir][1];
-          const int C[2] = {kDirs[dir][2], kDirs[dir][3]};
-          const float inv_dz_ab = 1.0f / (g.z_layer[B] - g.z_layer[A]);
-          for (int ja = 0; ja < wn[A]; ++ja) {
-            const int64_t iA = wf[A] + ja;
-            if (!y_ok(hyb, hye, iA, yl[A])) continue;
-            const float mA = hu[iA] + yl[A] * g.dxdy[A];
-            for (int jb = 0; jb < wn[B]; ++jb) {
-              const int64_t iB = wf[B] + jb;
-              if (!y_ok(hyb, hye, iB, yl[B])) continue;
-              const float mB = hu[iB] + yl[B] * g.dxdy[B];
-              const float slope = (mB - mA) * inv_dz_ab;
-              if (!(fabsf(slope - tx) <= p.slope_tol)) continue;
-              uint32_t mask[2];
-#pragma unroll
-              for (int k = 0; k < 2; ++k) {
-                const int Cl = C[k];
-                const float d = g.z_layer[Cl] - g.z_layer[A];
-                const float xt = mA + slope * d;
-                const float xv = mA + tx * d;
-                const float lo = fminf(xt, xv) - p.eps;
-                const float hi = fmaxf(xt, xv) + p.eps;
-                uint32_t mk = 0;
-                for (int j = 0; j < wn[Cl]; ++j) {
-                  const int64_t i = wf[Cl] + j;
-                  if (!y_ok(hyb, hye, i, yl[Cl])) continue;
-                  const float m = hu[i] + yl[Cl] * g.dxdy[Cl];
-                  if (lo <= m && m <= hi) mk |= 1u << j;
-                }
-                mask[k] = mk;
-              }
-              // every candidate: each completion panel one compatible hit or none, >= 3 hits
-              for (int k1 = -1; k1 < wn[C[0]]; ++k1) {
-                if (k1 >= 0 && !((mask[0] >> k1) & 1u)) continue;
-                for (int k2 = -1; k2 < wn[C[1]]; ++k2) {
-                  if (k2 >= 0 && !((mask[1] >> k2) & 1u)) continue;
-                  const int n = 2 + (k1 >= 0) + (k2 >= 0);
-                  if (n < 3) continue;
-                  int32_t idx[kLayers];
-#pragma unroll
-                  for (int l = 0; l < kLayers; ++l) idx[l] = -1;
-                  idx[A] = (int32_t)iA;
-                  idx[B] = (int32_t)iB;
-                  if (k1 >= 0) idx[C[0]] = (int32_t)(wf[C[0]] + k1);
-                  if (k2 >= 0) idx[C[1]] = (int32_t)(wf[C[1]] + k2);
-                  float q, c2;
-                  fit(g, xs, yl, hu, hw, idx, q, c2);
-                  if (better(n, c2, idx, best)) {
-                    best.n = n;
-                    best.q = q;
-                    best.chi2 = c2;
-#pragma unroll
-                    for (int l = 0; l < kLayers; ++l) best.idx[l] = idx[l];
-                  }
-                }
-              }
-            }
-          }
-        }
-      }
-
-#pragma unroll
-      for (int l = 0; l < kLayers; ++l) hit_idx[(int64_t)t * kLayers + l] = best.idx[l];
-      qop[t] = best.q;
-      chi2[t] = best.chi2;
-      nhits[t] = best.n;
-      if (windows) {
-#pragma unroll
-        for (int l = 0; l < kLayers; ++l) {
-          const int64_t o = ((int64_t)t * kLayers + l) * 2;
-          windows[o] = active ? (int16_t)(wf[l] - layer_first[l]) : (int16_t)-1;
-          windows[o + 1] = (int16_t)wn[l];
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t k = k0 + q * bs + tid;
+          if (k < nh) s_u[k] = v[q];
         }
       }
     }
+    if (overflow && tid == 0) raise_flag(flags, UTC_FLAG_LAYER_OVERFLOW);
+    __syncthreads();
+    EventView ev;
+    ev.u_lds = s_u;
+    ev.u_glb = hu;
+    ev.w_lds = nullptr;
+    ev.w_glb = hw;
+    ev.yb_glb = hyb;
+    ev.ye_glb = hye;
+    ev.hoff = s_hoff;
+    ev.first = H;
+    ev.overflow = overflow;
+    const uint32_t t0 = velo_offsets[e], t1 = velo_offsets[e + 1];
+    const uint32_t ngroups = (t1 - t0 + kGroupTracks - 1) / kGroupTracks;
+    if (staged) {
+      for (uint32_t grp = wid; grp < ngroups; grp += nwaves)
+        compass_group<true, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io);
+    } else {
+      for (uint32_t grp = wid; grp < ngroups; grp += nwaves)
+        compass_group<false, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io);
+    }
+    __syncthreads();
   }
+}
+
+size_t compass_lds_bytes(int S, int max_hits, int waves, int u_cap) {
+  const size_t hoff = 4 * (size_t)(((kLayers * S + 1) + 3) & ~3);
+  return hoff + 4 * (size_t)u_cap + (size_t)waves * group_scratch_bytes(max_hits);
 }
 
 }  // namespace utc
@@ -284,9 +136,19 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   p.slope_tol = params->slope_tol;
   p.eps = params->completion_tol;
   const int block = launch ? launch->block : 256;
+  const int waves = block / kWave;
+  // stage u of events up to u_cap hits, keeping the workgroup's LDS at or under 40 KiB so that
+  // four workgroups share a CU; larger events search global memory
+  const size_t fixed = compass_lds_bytes(g.S, p.max_hits, waves, 0);
+  int u_cap = fixed < 40 * 1024 ? (int)((40 * 1024 - fixed) / sizeof(float)) / 64 * 64 : 0;
+  const size_t lds = compass_lds_bytes(g.S, p.max_hits, waves, u_cap);
+  if (lds > 160 * 1024) return UTC_ERR_ARG;
+  (void)hipGetLastError();  // report only errors of this call
   const int grid = (launch && launch->grid > 0) ? launch->grid : n_events;
-  hipLaunchKernelGGL(k_compass_thread, dim3(grid), dim3(block), 0, stream, g, p, n_events,
-                     hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end, vx, vy, vtx, vty,
-                     velo_offsets, hit_idx, qop, chi2, nhits, windows, error_flags);
+  TrackIO io{vx, vy, vtx, vty, hit_idx, qop, chi2, nhits, windows};
+  if (!allow_dynamic_lds(reinterpret_cast<const void*>(k_compass), lds)) return UTC_ERR_HIP;
+  hipLaunchKernelGGL(k_compass, dim3(grid), dim3(block), lds, stream, g, p, n_events, hit_offsets,
+                     hit_u, hit_weight, hit_y_begin, hit_y_end, velo_offsets, io, error_flags,
+                     u_cap);
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
 }

@@ -1,0 +1,401 @@
+// Compass tracklet search for a group of 16 VELO tracks by one wavefront (Section V of the paper):
+// the device code shared by the stand-alone compass_find kernel and the fused kernel.
+//
+// Lane layout for windows: lane = 4*t + l (track t of the group, layer l).  Each lane extrapolates
+// its track to its layer, does the binary searches for its window and copies the window's hits
+// (x at the track's y, weight or -1 when the strip does not cover the track's y) into an LDS tile.
+// Tracklets: the (anchor A, anchor B) pairs of all 16 tracks are flattened over the lanes; each
+// lane tests its pair's slope, builds the completion masks, fits every candidate and folds the
+// candidate's 64-bit selection key into the track's minimum with an LDS atomic.  The key orders
+// candidates exactly like the reference selection (more hits, then lower chi2, then the
+// lexicographically smaller hit-index tuple), so the minimum is the same for every schedule.
+#pragma once
+
+#include "common.hpp"
+
+namespace utc {
+
+constexpr int kGroupTracks = 16;
+
+struct CPar {
+  float W;            // window half-width (mm)
+  int max_hits;       // per-layer window cap (<= 32)
+  int half;           // (n_sectors_search - 1) / 2
+  float slope_tol;
+  float eps;          // completion interval margin (mm)
+};
+
+// Hits of the current event as seen by the search.  kULds / kWLds: u / weight read from LDS
+// (event-local index) rather than global memory; the choice is a template parameter so that each
+// instantiation addresses one memory space directly.  Hit offsets of the event's 4*S banks are in
+// LDS, relative to the event's first hit.
+struct EventView {
+  const float* u_lds;          // staged u (event-local index)
+  const float* u_glb;          // global u
+  const float* w_lds;          // staged weights (event-local index)
+  const float* w_glb;
+  const float* yb_glb;         // nullptr: every strip spans [g.y_begin, g.y_end]
+  const float* ye_glb;
+  const uint32_t* hoff;        // [4S+1] event-local first hit of each bank
+  int64_t first;               // global index of the event's first hit
+  bool overflow;               // an (event, layer) holds more than 32767 hits
+};
+
+template <bool kULds>
+__device__ inline float ev_u(const EventView& ev, uint32_t k) {
+  if constexpr (kULds) return ev.u_lds[k];
+  else return ev.u_glb[ev.first + k];
+}
+
+template <bool kWLds>
+__device__ inline float ev_w(const EventView& ev, uint32_t k) {
+  if constexpr (kWLds) return ev.w_lds[k];
+  else return ev.w_glb[ev.first + k];
+}
+
+// Per-wavefront LDS of the group.  Tile entries are slot-major (slot j of lane 4t+l at
+// j*64 + 4t + l) so that the 64 lanes filling one slot hit 64 different banks.
+struct GroupScratch {
+  float* tm;          // [max_hits][64] x at the track's y of each window hit
+  float* tw;          // [max_hits][64] weight, -1 when unusable
+  float* xs;          // [64] straight-line x at each layer
+  float* tx;          // [16] VELO slope tx of each track
+  int32_t* nwin;      // [64] window sizes
+  unsigned long long* best;  // [16] selection key minimum
+  uint32_t* poff;     // [17] pair offsets of the tracks
+  uint32_t* bp;       // [64] batch of anchor pairs that passed the slope test: t | jA<<8 | jB<<16
+  uint32_t* bm1;      // [64] their completion masks in layer C1
+  uint32_t* bm2;      // [64] their completion masks in layer C2
+  uint32_t* boff;     // [65] candidate offsets of the batch
+};
+
+__host__ __device__ inline size_t group_scratch_bytes(int max_hits) {
+  const size_t b = 8 * kGroupTracks + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
+                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65;
+  return (b + 15) / 16 * 16;
+}
+
+__device__ inline GroupScratch carve_group(char* p, int max_hits) {
+  GroupScratch s;
+  s.best = reinterpret_cast<unsigned long long*>(p);
+  s.tm = reinterpret_cast<float*>(s.best + kGroupTracks);
+  s.tw = s.tm + 64 * max_hits;
+  s.xs = s.tw + 64 * max_hits;
+  s.tx = s.xs + 64;
+  s.nwin = reinterpret_cast<int32_t*>(s.tx + kGroupTracks);
+  s.poff = reinterpret_cast<uint32_t*>(s.nwin + 64);
+  s.bp = s.poff + kGroupTracks + 1;
+  s.bm1 = s.bp + 64;
+  s.bm2 = s.bm1 + 64;
+  s.boff = s.bm2 + 64;
+  return s;
+}
+
+__device__ inline int tile_at(int t, int l, int j) { return j * 64 + t * 4 + l; }
+
+// anchor A, anchor B, completion C1, completion C2; forward then backward (panel order reversed)
+__device__ inline void dir_layers(int dir, int& A, int& B, int& C1, int& C2) {
+  if (dir == 0) { A = 0; B = 2; C1 = 1; C2 = 3; }
+  else { A = 3; B = 1; C1 = 2; C2 = 0; }
+}
+
+constexpr unsigned long long kNoKey = ~0ull;
+
+// Fit of one candidate (codes: window slot + 1 per layer, 0 = no hit): one-parameter weighted
+// least squares in q/p with the VELO state fixed; layers summed in order 0..3.
+__device__ inline void fit_codes(const Geom& g, const GroupScratch& s, int t,
+                                 const uint32_t code[4], float& q_out, float& chi2_out) {
+  float r[kLayers], w[kLayers];
+  float Sar = 0.0f, Saa = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLayers; ++l) {
+    if (code[l] == 0) continue;
+    const int o = tile_at(t, l, (int)code[l] - 1);
+    w[l] = s.tw[o];
+    r[l] = s.tm[o] - s.xs[t * 4 + l];
+    const float wa = w[l] * g.a_kick[l];
+    Sar = Sar + wa * r[l];
+    Saa = Saa + wa * g.a_kick[l];
+  }
+  const float q = Sar / Saa;
+  float chi2 = 0.0f;
+#pragma unroll
+  for (int l = 0; l < kLayers; ++l) {
+    if (code[l] == 0) continue;
+    const float e = r[l] - g.a_kick[l] * q;
+    chi2 = chi2 + (w[l] * e) * e;
+  }
+  q_out = q;
+  chi2_out = chi2;
+}
+
+__device__ inline unsigned long long make_key(int nh, float chi2, const uint32_t code[4]) {
+  return ((unsigned long long)(nh == 4 ? 0u : 1u) << 63) |
+         ((unsigned long long)__float_as_uint(chi2) << 24) |
+         ((unsigned long long)code[0] << 18) | ((unsigned long long)code[1] << 12) |
+         ((unsigned long long)code[2] << 6) | (unsigned long long)code[3];
+}
+
+// Position of the n-th (from 0) set bit of m.
+__device__ inline uint32_t nth_set_bit(uint32_t m, uint32_t n) {
+  for (uint32_t i = 0; i < n; ++i) m &= m - 1;
+  return (uint32_t)__builtin_ctz(m);
+}
+
+// Anchor pair of a direction: slope of the two anchor hits and whether it passes the slope test.
+__device__ inline bool pair_slope(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
+                                  int B, int jA, int jB, float& mA, float& slope) {
+  const int oA = tile_at(t, A, jA), oB = tile_at(t, B, jB);
+  if (s.tw[oA] < 0.0f || s.tw[oB] < 0.0f) return false;
+  mA = s.tm[oA];
+  const float mB = s.tm[oB];
+  const float inv_dz_ab = 1.0f / (g.z_layer[B] - g.z_layer[A]);
+  slope = (mB - mA) * inv_dz_ab;
+  return fabsf(slope - s.tx[t]) <= p.slope_tol;
+}
+
+// Completion hits of a passing pair in layer Cl: inside the interval spanned by the pair-slope and
+// VELO-slope extrapolations from the first anchor, widened by the completion tolerance.
+__device__ inline uint32_t completion_mask(const Geom& g, const CPar& p, const GroupScratch& s,
+                                           int t, int A, int Cl, float mA, float slope) {
+  const float d = g.z_layer[Cl] - g.z_layer[A];
+  const float xt = mA + slope * d;
+  const float xv = mA + s.tx[t] * d;
+  const float lo = fminf(xt, xv) - p.eps;
+  const float hi = fmaxf(xt, xv) + p.eps;
+  uint32_t mk = 0;
+  const int n = s.nwin[t * 4 + Cl];
+  for (int j = 0; j < n; ++j) {
+    const int o = tile_at(t, Cl, j);
+    const float m = s.tm[o];
+    if (s.tw[o] >= 0.0f && lo <= m && m <= hi) mk |= 1u << j;
+  }
+  return mk;
+}
+
+// All candidates of one direction for the tracks with want_lane set (read on their layer-0 lane).
+// Pairs are flattened over the lanes; the pairs that pass the slope test are compacted into a batch,
+// their completion masks computed, and the batch's candidates flattened over the lanes again, so
+// that every lane fits a real candidate.  Each candidate's key is folded into its track's minimum.
+__device__ inline void run_direction(const Geom& g, const CPar& p, const GroupScratch& s, int dir,
+                                     bool want_lane) {
+  const int lane = lane_id();
+  const int t = lane >> 2, l = lane & 3;
+  int A, B, C1, C2;
+  dir_layers(dir, A, B, C1, C2);
+  const uint32_t cnt = (l == 0 && want_lane) ? (uint32_t)(s.nwin[t * 4 + A] * s.nwin[t * 4 + B]) : 0u;
+  uint32_t total;
+  const uint32_t off = wave_excl_scan(cnt, &total);
+  if (l == 0) s.poff[t] = off;
+  if (lane == 0) s.poff[kGroupTracks] = total;
+  wave_sync();
+  for (uint32_t base = 0; base < total; base += kWave) {
+    // slope test of one pair per lane
+    const uint32_t it = base + (uint32_t)lane;
+    bool pass = false;
+    uint32_t info = 0;
+    if (it < total) {
+      const int tt = (int)first_true(0, kGroupTracks, [&](int64_t k) { return s.poff[k + 1] > it; });
+      const uint32_t r = it - s.poff[tt];
+      const uint32_t nb = (uint32_t)s.nwin[tt * 4 + B];
+      const uint32_t jA = r / nb, jB = r - jA * nb;
+      float mA, slope;
+      pass = pair_slope(g, p, s, tt, A, B, (int)jA, (int)jB, mA, slope);
+      info = (uint32_t)tt | (jA << 8) | (jB << 16);
+    }
+    const uint64_t pm = ballot(pass);
+    const uint32_t np = (uint32_t)__popcll(pm);
+    if (np == 0) continue;
+    if (pass) s.bp[lanes_before(pm)] = info;
+    wave_sync();
+    // completion masks of the batch, one pair per lane
+    uint32_t ncand = 0;
+    if ((uint32_t)lane < np) {
+      const uint32_t b = s.bp[lane];
+      const int tt = (int)(b & 0xFFu);
+      const int jA = (int)((b >> 8) & 0xFFu), jB = (int)(b >> 16);
+      float mA, slope;
+      pair_slope(g, p, s, tt, A, B, jA, jB, mA, slope);
+      const uint32_t m1 = completion_mask(g, p, s, tt, A, C1, mA, slope);
+      const uint32_t m2 = completion_mask(g, p, s, tt, A, C2, mA, slope);
+      s.bm1[lane] = m1;
+      s.bm2[lane] = m2;
+      // every combination of (none or one compatible hit) per completion layer but (none, none)
+      ncand = ((uint32_t)__popc(m1) + 1u) * ((uint32_t)__popc(m2) + 1u) - 1u;
+    }
+    uint32_t ctot;
+    const uint32_t coff = wave_excl_scan(ncand, &ctot);
+    s.boff[lane] = coff;
+    if (lane == 0) s.boff[kWave] = ctot;
+    wave_sync();
+    // candidates of the batch, one per lane
+    for (uint32_t cb = 0; cb < ctot; cb += kWave) {
+      const uint32_t ci = cb + (uint32_t)lane;
+      if (ci < ctot) {
+        const uint32_t pi = (uint32_t)first_true(0, np, [&](int64_t k) { return s.boff[k + 1] > ci; });
+        const uint32_t rr = ci - s.boff[pi] + 1u;
+        const uint32_t m1 = s.bm1[pi], m2 = s.bm2[pi];
+        const uint32_t n2 = (uint32_t)__popc(m2) + 1u;
+        const uint32_t i1 = rr / n2, i2 = rr - i1 * n2;
+        const uint32_t k1 = i1 == 0 ? 0u : nth_set_bit(m1, i1 - 1) + 1u;
+        const uint32_t k2 = i2 == 0 ? 0u : nth_set_bit(m2, i2 - 1) + 1u;
+        const uint32_t b = s.bp[pi];
+        const int tt = (int)(b & 0xFFu);
+        const uint32_t jA = (b >> 8) & 0xFFu, jB = b >> 16;
+        uint32_t code[4];
+#pragma unroll
+        for (int q = 0; q < kLayers; ++q)
+          code[q] = q == A ? jA + 1u : q == B ? jB + 1u : q == C1 ? k1 : k2;
+        const int nh = 2 + (k1 != 0) + (k2 != 0);
+        float qop, chi2;
+        fit_codes(g, s, tt, code, qop, chi2);
+        atomicMin(&s.best[tt], make_key(nh, chi2, code));
+      }
+    }
+    wave_sync();
+  }
+  wave_sync();
+}
+
+}  // namespace utc
+
+namespace utc {
+
+struct TrackIO {
+  const float* vx;
+  const float* vy;
+  const float* vtx;
+  const float* vty;
+  int32_t* hit_idx;
+  float* qop;
+  float* chi2;
+  int32_t* nhits;
+  int16_t* windows;
+};
+
+// The whole search for tracks [tbase, min(tbase+16, t1)) of one event.
+template <bool kULds, bool kWLds>
+__device__ inline void compass_group(const Geom& g, const CPar& p, const EventView& ev,
+                                     const GroupScratch& s, uint32_t tbase, uint32_t t1,
+                                     const TrackIO& io)
+{
+  const int lane = lane_id();
+  const int t = lane >> 2, l = lane & 3;
+  const int S = g.S;
+  const int M = p.max_hits;
+  const uint32_t trk = tbase + (uint32_t)t;
+  const bool has = trk < t1;
+  float x0 = 0.0f, y0 = 0.0f, tx = 0.0f, ty = 0.0f;
+  if (has) {
+    x0 = io.vx[trk];
+    y0 = io.vy[trk];
+    tx = io.vtx[trk];
+    ty = io.vty[trk];
+  }
+  // straight-line extrapolation of the VELO state to this lane's layer
+  const float dz = g.z_layer[l] - g.z_velo;
+  const float xs = x0 + tx * dz;
+  const float yl = y0 + ty * dz;
+  const float up = xs - yl * g.dxdy[l];
+  // acceptance: inside the planes at the first and the last layer
+  const float u_max = g.u_min + (float)S * g.sector_width;
+  bool ok = true;
+  if (l == 0 || l == kLayers - 1)
+    ok = (g.y_begin <= yl && yl <= g.y_end) && (g.u_min <= up && up <= u_max);
+  const uint64_t okm = ballot(ok);
+  const bool active = has && !ev.overflow && ((okm >> (4 * t)) & 1ull) && ((okm >> (4 * t + 3)) & 1ull);
+
+  // window (Section V-A): central sector and neighbours, [up - W, up + W], nearest max_hits hits
+  uint32_t wf = 0;
+  int wn = 0;
+  if (active) {
+    const float ts = floorf((up - g.u_min) * g.inv_sector_width);
+    const int c = ts < 0.0f ? 0 : (ts > (float)(S - 1) ? S - 1 : (int)ts);
+    const int s_lo = c - p.half < 0 ? 0 : c - p.half;
+    const int s_hi = c + p.half > S - 1 ? S - 1 : c + p.half;
+    const uint32_t H0 = ev.hoff[l * S + s_lo], H1 = ev.hoff[l * S + s_hi + 1];
+    const float lo = up - p.W, hi = up + p.W;
+    uint32_t first = first_true_u32(H0, H1, [&](uint32_t k) { return ev_u<kULds>(ev, k) >= lo; });
+    uint32_t end = first_true_u32(first, H1, [&](uint32_t k) { return ev_u<kULds>(ev, k) > hi; });
+    if (end - first > (uint32_t)M) {
+      // the M nearest hits: the first start f whose left hit is no farther than the hit just past
+      // the window (identical to dropping the farther end one hit at a time, the right on a tie)
+      first = first_true_u32(first, end - (uint32_t)M, [&](uint32_t f) {
+        return (up - ev_u<kULds>(ev, f)) <= (ev_u<kULds>(ev, f + (uint32_t)M) - up);
+      });
+      end = first + (uint32_t)M;
+    }
+    wf = first;
+    wn = (int)(end - first);
+  }
+  s.nwin[lane] = wn;
+  s.xs[lane] = xs;
+  if (l == 0) {
+    s.tx[t] = tx;
+    s.best[t] = kNoKey;
+  }
+  // tile: x at the track's y and weight of each window hit; -1 marks a strip that does not cover y
+  const float g_yb = g.y_begin, g_ye = g.y_end;
+  for (int j0 = 0; j0 < wn; j0 += 8) {
+    float uu[8], ww[8], yb[8], ye[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t k = wf + (uint32_t)(j0 + q);
+      const bool in = j0 + q < wn;
+      uu[q] = 0.0f;
+      ww[q] = 0.0f;
+      yb[q] = g_yb;
+      ye[q] = g_ye;
+      if (in) {
+        uu[q] = ev_u<kULds>(ev, k);
+        ww[q] = ev_w<kWLds>(ev, k);
+        if (ev.yb_glb) {
+          yb[q] = ev.yb_glb[ev.first + k];
+          ye[q] = ev.ye_glb[ev.first + k];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (j0 + q < wn) {
+        s.tm[tile_at(t, l, j0 + q)] = uu[q] + yl * g.dxdy[l];
+        s.tw[tile_at(t, l, j0 + q)] = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
+      }
+    }
+  }
+  wave_sync();
+
+  // tracklets (Section V-B): forward anchors first; backward only where forward found nothing
+  run_direction(g, p, s, 0, active);
+  const bool need_back = active && s.best[t] == kNoKey;
+  if (wave_any(need_back)) run_direction(g, p, s, 1, need_back);
+
+  const unsigned long long key = active ? s.best[t] : kNoKey;
+  const bool found = key != kNoKey;
+  const uint32_t code = found ? (uint32_t)((key >> (6 * (3 - l))) & 63ull) : 0u;
+  if (has) {
+    io.hit_idx[(int64_t)trk * 4 + l] = code ? (int32_t)(ev.first + wf + code - 1) : -1;
+    if (io.windows) {
+      const int64_t o = ((int64_t)trk * 4 + l) * 2;
+      io.windows[o] = active ? (int16_t)(wf - ev.hoff[l * S]) : (int16_t)-1;
+      io.windows[o + 1] = (int16_t)wn;
+    }
+    if (l == 0) {
+      float q = 0.0f, c2 = 0.0f;
+      int nh = 0;
+      if (found) {
+        uint32_t codes[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) codes[k] = (uint32_t)((key >> (6 * (3 - k))) & 63ull);
+        fit_codes(g, s, t, codes, q, c2);
+        nh = (key >> 63) ? 3 : 4;
+      }
+      io.qop[trk] = q;
+      io.chi2[trk] = c2;
+      io.nhits[trk] = nh;
+    }
+  }
+  wave_sync();
+}
+
+}  // namespace utc

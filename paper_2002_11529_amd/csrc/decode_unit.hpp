@@ -1,0 +1,288 @@
+// Decoding of one (event, layer) unit by one wavefront: the device code shared by the stand-alone
+// decoder and the fused decode + Compass kernel.
+#pragma once
+
+#include "common.hpp"
+
+namespace utc {
+
+constexpr uint32_t kMaxBankWords = UTC_MAX_BANK_WORDS;
+constexpr int kCap = 768;            // raw words staged in LDS per chunk and wavefront
+
+struct HitsOut {
+  uint32_t* lhcbid;
+  float* z;
+  float* u;
+  float* y_begin;
+  float* y_end;
+  float* weight;
+};
+
+// Per-wavefront LDS scratch.
+struct WaveScratch {
+  uint32_t* off;    // [S+1] raw word offsets of the unit's banks
+  uint32_t* hb;     // [S+1] first hit of each bank inside the current chunk
+  uint16_t* raw;    // [kCap] staged raw words
+  uint32_t* key;    // [kCap] valid words in bank order as (word << 16) | index: the sort key
+  uint16_t* cbank;  // [kCap] bank of each valid word in bank order
+  uint16_t* mark;   // [kCap] bank start markers by raw position, then valid words before it
+};
+
+__host__ __device__ inline size_t wave_scratch_bytes(int S) {
+  const size_t b = 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(uint32_t) * (size_t)kCap +
+                   3 * sizeof(uint16_t) * (size_t)kCap;
+  return (b + 15) / 16 * 16;
+}
+
+__device__ inline WaveScratch carve_scratch(char* p, int S) {
+  WaveScratch w;
+  w.off = reinterpret_cast<uint32_t*>(p);
+  w.hb = w.off + (S + 1);
+  w.key = w.hb + (S + 1);
+  w.raw = reinterpret_cast<uint16_t*>(w.key + kCap);
+  w.cbank = w.raw + kCap;
+  w.mark = w.cbank + kCap;
+  return w;
+}
+
+__device__ inline bool bank_ok(uint32_t a, uint32_t e) { return e >= a && e - a <= kMaxBankWords; }
+
+struct UnitCount {
+  uint32_t T;       // valid words (hits) of the unit
+  bool bad;         // some bank is malformed: banks are then handled one by one
+  bool staged;      // all of the unit's words are already in ws.raw
+};
+
+// Offsets of the unit's banks to LDS, well-formedness checks, hit count; the words are staged in
+// LDS on the way when they fit.  Uniform across the wavefront.  With ws.raw == nullptr nothing is
+// staged (count only).
+__device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict__ words,
+                                       const uint32_t* __restrict__ bank_offsets, int64_t b0,
+                                       const WaveScratch& ws, uint32_t* flags)
+{
+  const int S = g.S;
+  const int lane = lane_id();
+  for (int s = lane; s <= S; s += kWave) ws.off[s] = bank_offsets[b0 + s];
+  wave_sync();
+  bool bad = false;
+  for (int s = lane; s < S; s += kWave) {
+    const uint32_t a = ws.off[s], e = ws.off[s + 1];
+    if (e < a) {
+      bad = true;
+      raise_flag(flags, UTC_FLAG_BANK_ORDER);
+    } else if (e - a > kMaxBankWords) {
+      bad = true;
+      raise_flag(flags, UTC_FLAG_BANK_SIZE);
+    }
+  }
+  UnitCount st;
+  st.bad = wave_any(bad);
+  st.T = 0;
+  st.staged = false;
+  if (!st.bad) {
+    const uint32_t w0 = ws.off[0];
+    const uint32_t nw = ws.off[S] - w0;
+    st.staged = ws.raw != nullptr && nw <= (uint32_t)kCap;
+    uint32_t c = 0;
+    for (uint32_t i0 = 0; i0 < nw; i0 += 8 * kWave) {
+      uint16_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t i = i0 + k * kWave + lane;
+        v[k] = i < nw ? words[w0 + i] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t i = i0 + k * kWave + lane;
+        if (st.staged && i < nw) ws.raw[i] = v[k];
+        c += (v[k] & 0xFu) != 0u;
+      }
+    }
+    st.T = wave_sum(c);
+  } else {
+    uint32_t c = 0;
+    for (int s = lane; s < S; s += kWave) {
+      const uint32_t a = ws.off[s], e = ws.off[s + 1];
+      if (bank_ok(a, e))
+        for (uint32_t i = a; i < e; ++i) c += (words[i] & 0xFu) != 0u;
+    }
+    st.T = wave_sum(c);
+  }
+  return st;
+}
+
+// Decode one raw word of sector s in layer `layer`.
+struct DecodedHit {
+  uint32_t lhcbid;
+  float u, w;
+};
+
+__device__ inline DecodedHit decode_word(const Geom& g, int layer, uint32_t s, uint32_t v) {
+  const uint32_t size = v & 0xFu, frac = (v >> 4) & 7u, strip = v >> 7;
+  DecodedHit d;
+  d.lhcbid = ((uint32_t)layer << 28) | (s << 12) | (strip << 3) | frac;
+  d.u = fmaf((float)(strip * 8u + frac), g.pitch8, g.u0[layer * g.S + (int)s]);
+  d.w = g.weight_by_size[size];
+  return d;
+}
+
+__device__ inline void store_hit(const Geom& g, int layer, const DecodedHit& d, int64_t h,
+                                 int64_t capacity, const HitsOut& out, uint32_t* flags) {
+  if (h >= capacity) {
+    raise_flag(flags, UTC_FLAG_CAPACITY);
+    return;
+  }
+  out.lhcbid[h] = d.lhcbid;
+  out.z[h] = g.z_layer[layer];
+  out.u[h] = d.u;
+  out.y_begin[h] = g.y_begin;
+  out.y_end[h] = g.y_end;
+  out.weight[h] = d.w;
+}
+
+// A bank too large for the LDS chunk: rank every hit against the whole bank in global memory.
+__device__ inline uint32_t big_bank(const Geom& g, const uint16_t* __restrict__ words, int layer,
+                                    uint32_t s, uint32_t a, uint32_t n, int64_t first_hit,
+                                    int64_t capacity, const HitsOut& out, uint32_t* flags,
+                                    float* lds_u, float* lds_w, uint32_t lds_first)
+{
+  const int lane = lane_id();
+  uint32_t nh = 0;
+  for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
+    const uint32_t i = i0 + lane;
+    const uint16_t v = i < n ? words[a + i] : (uint16_t)0;
+    nh += (uint32_t)__popcll(ballot((v & 0xFu) != 0u));
+  }
+  for (uint32_t i = lane; i < n; i += kWave) {
+    const uint16_t v = words[a + i];
+    if (!(v & 0xFu)) continue;
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint16_t o = words[a + j];
+      rank += ((o & 0xFu) != 0u) & ((o < v) | ((o == v) & (j < i)));
+    }
+    const DecodedHit d = decode_word(g, layer, s, v);
+    store_hit(g, layer, d, first_hit + rank, capacity, out, flags);
+    if (lds_u) {
+      lds_u[lds_first + rank] = d.u;
+      lds_w[lds_first + rank] = d.w;
+    }
+  }
+  return nh;
+}
+
+// Compaction, sort and store of the unit's hits, first hit `base`.  When lds_u is given,
+// u and weight of hit k of the unit are also written to lds_u/lds_w[lds_first + k].
+__device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ words, int layer,
+                                  int64_t b0, uint32_t base, const UnitCount& st,
+                                  const WaveScratch& ws, int64_t capacity,
+                                  uint32_t* __restrict__ hit_offsets, const HitsOut& out,
+                                  uint32_t* flags, float* lds_u, float* lds_w, uint32_t lds_first)
+{
+  const int S = g.S;
+  const int lane = lane_id();
+  uint32_t local = 0;
+  int c0 = 0;
+  while (c0 < S) {
+    const uint32_t a0 = ws.off[c0], e0 = ws.off[c0 + 1];
+    int c1;
+    if (st.bad) {
+      if (!bank_ok(a0, e0)) {
+        if (lane == 0) hit_offsets[b0 + c0] = base + local;
+        ++c0;
+        continue;
+      }
+      c1 = e0 - a0 > (uint32_t)kCap ? c0 : c0 + 1;
+    } else {
+      // the longest run of banks from c0 whose words fit in the staging buffer
+      c1 = (int)first_true(c0 + 1, S + 1, [&](int64_t b) { return ws.off[b] - a0 > (uint32_t)kCap; }) - 1;
+    }
+    if (c1 == c0) {
+      if (lane == 0) hit_offsets[b0 + c0] = base + local;
+      local += big_bank(g, words, layer, (uint32_t)c0, a0, e0 - a0, (int64_t)base + local, capacity,
+                        out, flags, lds_u, lds_w, lds_first + local);
+      wave_sync();
+      ++c0;
+      continue;
+    }
+    const uint32_t n = ws.off[c1] - a0;
+    if (!st.staged) {
+      for (uint32_t i0 = 0; i0 < n; i0 += 8 * kWave) {
+        uint16_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t i = i0 + k * kWave + lane;
+          v[k] = i < n ? words[a0 + i] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t i = i0 + k * kWave + lane;
+          if (i < n) ws.raw[i] = v[k];
+        }
+      }
+    }
+    // bank start markers (bank + 1 at the first word of every non-empty bank of the chunk)
+    for (uint32_t i = lane; i < n; i += kWave) ws.mark[i] = 0;
+    wave_sync();
+    for (int b = c0 + lane; b < c1; b += kWave)
+      if (ws.off[b + 1] > ws.off[b]) ws.mark[ws.off[b] - a0] = (uint16_t)(b + 1);
+    wave_sync();
+
+    // stable compaction of the valid words, each with its bank (running maximum of the markers);
+    // the marker slot is then reused for the number of valid words before that raw position
+    uint32_t run = 0;
+    uint32_t bank_carry = 0;
+    for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
+      const uint32_t i = i0 + lane;
+      const uint16_t v = i < n ? ws.raw[i] : (uint16_t)0;
+      const bool valid = (v & 0xFu) != 0u;
+      uint32_t bk = i < n ? (uint32_t)ws.mark[i] : 0u;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t y = __shfl_up(bk, o, kWave);
+        if (lane >= o) bk = bk > y ? bk : y;
+      }
+      bk = bk > bank_carry ? bk : bank_carry;
+      bank_carry = wave_bcast(bk, kWave - 1);
+      const uint64_t m = ballot(valid);
+      const uint32_t pos = run + lanes_before(m);
+      if (i < n) ws.mark[i] = (uint16_t)pos;
+      if (valid) {
+        ws.key[pos] = ((uint32_t)v << 16) | pos;
+        ws.cbank[pos] = (uint16_t)(bk - 1);
+      }
+      run += (uint32_t)__popcll(m);
+    }
+    const uint32_t nh = run;
+    wave_sync();
+    for (int b = c0 + lane; b <= c1; b += kWave) {
+      const uint32_t r = ws.off[b] - a0;
+      ws.hb[b] = r < n ? (uint32_t)ws.mark[r] : nh;
+    }
+    wave_sync();
+    for (int b = c0 + lane; b < c1; b += kWave) hit_offsets[b0 + b] = base + local + ws.hb[b];
+
+    // each hit's rank in its bank by (word, position): sorted by word value, ties in bank order;
+    // the hit is decoded and stored straight to its sorted slot (the 64 lanes cover a contiguous
+    // range of the output, permuted inside each bank)
+    for (uint32_t k = lane; k < nh; k += kWave) {
+      const int bk = ws.cbank[k];
+      const uint32_t mine = ws.key[k];
+      const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
+      uint32_t rank = 0;
+      for (uint32_t j = lo; j < hi; ++j) rank += ws.key[j] < mine;
+      const uint32_t slot = lo + rank;
+      const DecodedHit d = decode_word(g, layer, (uint32_t)bk, mine >> 16);
+      store_hit(g, layer, d, (int64_t)base + local + slot, capacity, out, flags);
+      if (lds_u) {
+        lds_u[lds_first + local + slot] = d.u;
+        lds_w[lds_first + local + slot] = d.w;
+      }
+    }
+    local += nh;
+    c0 = c1;
+    wave_sync();
+  }
+}
+
+}  // namespace utc

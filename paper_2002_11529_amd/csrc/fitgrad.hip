@@ -12,7 +12,7 @@ namespace utc {
 
 constexpr double kFix = 1099511627776.0;           // 2^40
 constexpr double kTwo32 = 4294967296.0;            // 2^32
-constexpr int kMaxLdsSectors = 4 * 1024;           // 4*S sums held in LDS (16 B each)
+constexpr int kMaxRows = 512;                      // workgroups of the adjoint kernel (partial rows)
 
 // Split x * 2^40 into hi * 2^32 + lo with 0 <= lo < 2^32 (lo rounded to an integer).
 __device__ inline void to_fixed(double x, uint64_t& hi_out, uint64_t& lo_out) {
@@ -28,33 +28,30 @@ __device__ inline double from_fixed(uint64_t hi, uint64_t lo) {
   return ((double)(int64_t)hi * kTwo32 + (double)lo) / kFix;
 }
 
-// acc layout: [2*k] = hi, [2*k+1] = lo for k in 0 .. 4S (index 4S is the total chi2)
-__global__ void k_fitgrad_clear(uint64_t* acc, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc[i] = 0;
-}
-
-__global__ void __launch_bounds__(256)
+// Per-workgroup partial sums: workgroup b writes column b of part[2*(4S+1)][grid], the (hi, lo)
+// pairs of the 4S sector sums and, last, of the total chi2.  Every workgroup writes its whole
+// column, so no clearing and no global atomics.
+__global__ void __launch_bounds__(1024)
 k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, int64_t n_hits,
           const float* __restrict__ hu, const float* __restrict__ hw,
           const uint32_t* __restrict__ hid, const float* __restrict__ vx,
           const float* __restrict__ vy, const float* __restrict__ vtx,
           const float* __restrict__ vty, const float* __restrict__ qop,
           const float* __restrict__ offsets, float m2s, float* __restrict__ chi2_track,
-          float* __restrict__ grad_qop, bool want_offsets, bool want_total, bool lds,
-          uint64_t* acc)
+          float* __restrict__ grad_qop, bool want_sums, uint64_t* __restrict__ part)
 {
-  extern __shared__ uint64_t s_acc[];  // [2 * (4S + 1)] when `lds`
+  extern __shared__ uint64_t s_acc[];  // [2 * (4S + 1)] when want_sums
   const int S = g.S;
   const int n_sums = kLayers * S + 1;
-  if (lds) {
+  if (want_sums) {
     for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x) s_acc[i] = 0;
     __syncthreads();
   }
-  uint64_t* sums = lds ? s_acc : acc;
   double dz[kLayers];
 #pragma unroll
   for (int l = 0; l < kLayers; ++l) dz[l] = (double)g.z_layer[l] - (double)g.z_velo;
 
+  uint64_t tot_hi = 0, tot_lo = 0;  // this thread's share of the total chi2, fixed point
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tracks;
        t += (int64_t)gridDim.x * blockDim.x) {
     const double x0 = vx[t], y0 = vy[t], tx = vtx[t], ty = vty[t];
@@ -74,41 +71,63 @@ k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, i
       const float wr = hw[h] * r;
       c2 = c2 + wr * r;
       gq = gq + wr * g.a_kick[l];
-      if (want_offsets) {
+      if (want_sums) {
         uint64_t hi, lo;
         to_fixed((double)wr, hi, lo);
-        atomicAdd((unsigned long long*)&sums[2 * sec], (unsigned long long)hi);
-        atomicAdd((unsigned long long*)&sums[2 * sec + 1], (unsigned long long)lo);
+        atomicAdd((unsigned long long*)&s_acc[2 * sec], (unsigned long long)hi);
+        atomicAdd((unsigned long long*)&s_acc[2 * sec + 1], (unsigned long long)lo);
       }
     }
     if (chi2_track) chi2_track[t] = c2;
     if (grad_qop) grad_qop[t] = m2s * gq;
-    if (want_total) {
+    if (want_sums) {
       uint64_t hi, lo;
       to_fixed((double)c2, hi, lo);
-      atomicAdd((unsigned long long*)&sums[2 * (n_sums - 1)], (unsigned long long)hi);
-      atomicAdd((unsigned long long*)&sums[2 * (n_sums - 1) + 1], (unsigned long long)lo);
+      tot_hi += hi;
+      tot_lo += lo;
     }
   }
-  if (lds) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x) {
-      const uint64_t v = s_acc[i];
-      if (v) atomicAdd((unsigned long long*)&acc[i], (unsigned long long)v);
-    }
+  if (!want_sums) return;
+  // integer sums over the wavefront, then one LDS atomic pair per wavefront
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    tot_hi += __shfl_xor(tot_hi, o, kWave);
+    tot_lo += __shfl_xor(tot_lo, o, kWave);
   }
+  if (lane_id() == 0) {
+    atomicAdd((unsigned long long*)&s_acc[2 * (n_sums - 1)], (unsigned long long)tot_hi);
+    atomicAdd((unsigned long long*)&s_acc[2 * (n_sums - 1) + 1], (unsigned long long)tot_lo);
+  }
+  __syncthreads();
+  // column blockIdx.x of the sum-major partial array part[2*n_sums][gridDim.x]
+  for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x)
+    part[(size_t)i * gridDim.x + blockIdx.x] = s_acc[i];
 }
 
-__global__ void k_fitgrad_finalize(const uint64_t* __restrict__ acc, int n_sums, double scale2,
-                                   float* __restrict__ grad_offsets, double* __restrict__ chi2_total)
+// One wavefront per sum: add the workgroups' partials (integers, so in any order) and convert.
+__global__ void k_fitgrad_finalize(const uint64_t* __restrict__ part, int n_rows, int n_sums,
+                                   double scale2, float* __restrict__ grad_offsets,
+                                   double* __restrict__ chi2_total)
 {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sums; i += gridDim.x * blockDim.x) {
-    const double v = from_fixed(acc[2 * i], acc[2 * i + 1]);
-    if (i == n_sums - 1) {
-      if (chi2_total) *chi2_total = v;
-    } else if (grad_offsets) {
-      grad_offsets[i] = (float)(scale2 * v);
-    }
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (i >= n_sums) return;
+  const int lane = lane_id();
+  uint64_t hi = 0, lo = 0;
+  for (int r = lane; r < n_rows; r += kWave) {
+    hi += part[(size_t)(2 * i) * n_rows + r];
+    lo += part[(size_t)(2 * i + 1) * n_rows + r];
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    hi += __shfl_xor(hi, o, kWave);
+    lo += __shfl_xor(lo, o, kWave);
+  }
+  if (lane != 0) return;
+  const double v = from_fixed(hi, lo);
+  if (i == n_sums - 1) {
+    if (chi2_total) *chi2_total = v;
+  } else if (grad_offsets) {
+    grad_offsets[i] = (float)(scale2 * v);
   }
 }
 
@@ -119,14 +138,14 @@ using namespace utc;
 extern "C" size_t compass_fit_grad_workspace_bytes(int32_t n_sectors)
 {
   if (n_sectors < 1) return 0;
-  const size_t n = 2 * ((size_t)kLayers * n_sectors + 1) * sizeof(uint64_t);
+  const size_t n = (size_t)kMaxRows * 2 * ((size_t)kLayers * n_sectors + 1) * sizeof(uint64_t);
   return (n + 255) / 256 * 256;
 }
 
 extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks,
                                        const int32_t* track_hit_idx, int64_t n_hits,
-                                       const float* hit_u,
-                                       const float* hit_weight, const uint32_t* hit_lhcbid,
+                                       const float* hit_u, const float* hit_weight,
+                                       const uint32_t* hit_lhcbid,
                                        const float* vx, const float* vy, const float* vtx,
                                        const float* vty, const float* qop, const float* offsets,
                                        float grad_scale, float* chi2_track, double* chi2_total,
@@ -144,33 +163,22 @@ extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_track
   const Geom g = make_geom(*geom);
   const int S = geom->n_sectors;
   const int n_sums = kLayers * S + 1;
-  uint64_t* acc = static_cast<uint64_t*>(workspace);
-  const bool want_offsets = grad_offsets != nullptr;
-  const bool want_total = chi2_total != nullptr;
+  uint64_t* part = static_cast<uint64_t*>(workspace);
+  const bool want_sums = grad_offsets != nullptr || chi2_total != nullptr;
   const float m2s = -2.0f * grad_scale;
-  if (want_offsets || want_total)
-    hipLaunchKernelGGL(k_fitgrad_clear, dim3((2 * n_sums + 255) / 256), dim3(256), 0, stream, acc,
-                       2 * n_sums);
-  if (n_tracks > 0) {
-    const int block = 256;
-    int64_t blocks = (n_tracks + block - 1) / block;
-    if (blocks > 2048) blocks = 2048;
-    const bool use_lds = (want_offsets || want_total) && n_sums <= kMaxLdsSectors + 1;
-    const size_t lds = use_lds ? 2 * (size_t)n_sums * sizeof(uint64_t) : 0;
-    if (lds > 64 * 1024) {
-      static bool attr_set = false;
-      if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_fitgrad),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-      }
-    }
-    hipLaunchKernelGGL(k_fitgrad, dim3((unsigned)blocks), dim3(block), lds, stream, g, n_tracks,
-                       track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop, offsets,
-                       m2s, chi2_track, grad_qop, want_offsets, want_total, use_lds, acc);
-  }
-  if (want_offsets || want_total)
-    hipLaunchKernelGGL(k_fitgrad_finalize, dim3((n_sums + 255) / 256), dim3(256), 0, stream, acc,
-                       n_sums, -2.0 * (double)grad_scale, grad_offsets, chi2_total);
+  const size_t lds = want_sums ? 2 * (size_t)n_sums * sizeof(uint64_t) : 0;
+  if (lds > 160 * 1024) return UTC_ERR_ARG;
+  (void)hipGetLastError();  // report only errors of this call
+  const int block = 1024;
+  int64_t blocks = (n_tracks + block - 1) / block;
+  if (blocks > kMaxRows) blocks = kMaxRows;
+  if (blocks < 1) blocks = 1;
+  if (!allow_dynamic_lds(reinterpret_cast<const void*>(k_fitgrad), lds)) return UTC_ERR_HIP;
+  hipLaunchKernelGGL(k_fitgrad, dim3((unsigned)blocks), dim3(block), lds, stream, g, n_tracks,
+                     track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop,
+                     offsets, m2s, chi2_track, grad_qop, want_sums, part);
+  if (want_sums)
+    hipLaunchKernelGGL(k_fitgrad_finalize, dim3((n_sums + 3) / 4), dim3(256), 0, stream, part,
+                       (int)blocks, n_sums, -2.0 * (double)grad_scale, grad_offsets, chi2_total);
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
 }

@@ -70,7 +70,7 @@ def test_pileup_sampled_events():
     assert_compass_equal(r, c, b, d)
 
 
-@pytest.mark.parametrize("launch", [dict(block=64), dict(block=128, grid=7), dict(block=1024, grid=3)])
+@pytest.mark.parametrize("launch", [dict(block=64), dict(block=128, grid=7), dict(block=512, grid=3)])
 def test_decode_launch_shapes_agree(launch):
     b = synth.generate("batched", n_events=60, with_truth=False)
     h0, r0, *_ = gpu_run(b)
