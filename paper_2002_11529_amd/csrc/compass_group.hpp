@@ -173,12 +173,13 @@ __device__ inline uint32_t completion_mask(const Geom& g, const CPar& p, const G
   return mk;
 }
 
-// All candidates of one direction for the tracks with want_lane set (read on their layer-0 lane).
-// Pairs are flattened over the lanes; the pairs that pass the slope test are compacted into a batch,
-// their completion masks computed, and the batch's candidates flattened over the lanes again, so
-// that every lane fits a real candidate.  Each candidate's key is folded into its track's minimum.
+// The candidates of one direction with `nhits` hits (4: both completion layers; 3: one of them) for
+// the tracks with want_lane set (read on their layer-0 lane).  Anchor pairs are flattened over the
+// lanes; the pairs that pass the slope test are compacted into a batch, their completion masks
+// computed, and the batch's candidates flattened over the lanes again, so that every lane fits a
+// real candidate.  Each candidate's key is folded into its track's minimum.
 __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupScratch& s, int dir,
-                                     bool want_lane) {
+                                     int nhits, bool want_lane) {
   const int lane = lane_id();
   const int t = lane >> 2, l = lane & 3;
   int A, B, C1, C2;
@@ -195,7 +196,8 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
     bool pass = false;
     uint32_t info = 0;
     if (it < total) {
-      const int tt = (int)first_true(0, kGroupTracks, [&](int64_t k) { return s.poff[k + 1] > it; });
+      const int tt = (int)first_true_u32(0u, (uint32_t)kGroupTracks,
+                                         [&](uint32_t k) { return s.poff[k + 1] > it; });
       const uint32_t r = it - s.poff[tt];
       const uint32_t nb = (uint32_t)s.nwin[tt * 4 + B];
       const uint32_t jA = r / nb, jB = r - jA * nb;
@@ -220,8 +222,8 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
       const uint32_t m2 = completion_mask(g, p, s, tt, A, C2, mA, slope);
       s.bm1[lane] = m1;
       s.bm2[lane] = m2;
-      // every combination of (none or one compatible hit) per completion layer but (none, none)
-      ncand = ((uint32_t)__popc(m1) + 1u) * ((uint32_t)__popc(m2) + 1u) - 1u;
+      const uint32_t n1 = (uint32_t)__popc(m1), n2 = (uint32_t)__popc(m2);
+      ncand = nhits == 4 ? n1 * n2 : n1 + n2;
     }
     uint32_t ctot;
     const uint32_t coff = wave_excl_scan(ncand, &ctot);
@@ -232,13 +234,20 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
     for (uint32_t cb = 0; cb < ctot; cb += kWave) {
       const uint32_t ci = cb + (uint32_t)lane;
       if (ci < ctot) {
-        const uint32_t pi = (uint32_t)first_true(0, np, [&](int64_t k) { return s.boff[k + 1] > ci; });
-        const uint32_t rr = ci - s.boff[pi] + 1u;
+        const uint32_t pi = first_true_u32(0u, np, [&](uint32_t k) { return s.boff[k + 1] > ci; });
+        const uint32_t rr = ci - s.boff[pi];
         const uint32_t m1 = s.bm1[pi], m2 = s.bm2[pi];
-        const uint32_t n2 = (uint32_t)__popc(m2) + 1u;
-        const uint32_t i1 = rr / n2, i2 = rr - i1 * n2;
-        const uint32_t k1 = i1 == 0 ? 0u : nth_set_bit(m1, i1 - 1) + 1u;
-        const uint32_t k2 = i2 == 0 ? 0u : nth_set_bit(m2, i2 - 1) + 1u;
+        uint32_t k1, k2;  // window slot + 1 of the completion hits, 0 = none
+        if (nhits == 4) {
+          const uint32_t n2 = (uint32_t)__popc(m2);
+          const uint32_t i1 = rr / n2;
+          k1 = nth_set_bit(m1, i1) + 1u;
+          k2 = nth_set_bit(m2, rr - i1 * n2) + 1u;
+        } else {
+          const uint32_t n1 = (uint32_t)__popc(m1);
+          k1 = rr < n1 ? nth_set_bit(m1, rr) + 1u : 0u;
+          k2 = rr < n1 ? 0u : nth_set_bit(m2, rr - n1) + 1u;
+        }
         const uint32_t b = s.bp[pi];
         const int tt = (int)(b & 0xFFu);
         const uint32_t jA = (b >> 8) & 0xFFu, jB = b >> 16;
@@ -246,15 +255,24 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
 #pragma unroll
         for (int q = 0; q < kLayers; ++q)
           code[q] = q == A ? jA + 1u : q == B ? jB + 1u : q == C1 ? k1 : k2;
-        const int nh = 2 + (k1 != 0) + (k2 != 0);
         float qop, chi2;
         fit_codes(g, s, tt, code, qop, chi2);
-        atomicMin(&s.best[tt], make_key(nh, chi2, code));
+        atomicMin(&s.best[tt], make_key(nhits, chi2, code));
       }
     }
     wave_sync();
   }
   wave_sync();
+}
+
+// One direction: the 4-hit candidates first; a 3-hit candidate can never be selected over a 4-hit
+// one, so 3-hit candidates are only searched for the tracks without a 4-hit candidate.
+__device__ inline void search_direction(const Geom& g, const CPar& p, const GroupScratch& s,
+                                        int dir, bool want_lane) {
+  const int t = lane_id() >> 2;
+  run_direction(g, p, s, dir, 4, want_lane);
+  const bool need3 = want_lane && s.best[t] == kNoKey;
+  if (wave_any(need3)) run_direction(g, p, s, dir, 3, need3);
 }
 
 }  // namespace utc
@@ -336,10 +354,10 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   }
   // tile: x at the track's y and weight of each window hit; -1 marks a strip that does not cover y
   const float g_yb = g.y_begin, g_ye = g.y_end;
-  for (int j0 = 0; j0 < wn; j0 += 8) {
-    float uu[8], ww[8], yb[8], ye[8];
+  for (int j0 = 0; j0 < wn; j0 += 4) {
+    float uu[4], ww[4], yb[4], ye[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const uint32_t k = wf + (uint32_t)(j0 + q);
       const bool in = j0 + q < wn;
       uu[q] = 0.0f;
@@ -356,7 +374,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
       }
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       if (j0 + q < wn) {
         s.tm[tile_at(t, l, j0 + q)] = uu[q] + yl * g.dxdy[l];
         s.tw[tile_at(t, l, j0 + q)] = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
@@ -366,9 +384,9 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   wave_sync();
 
   // tracklets (Section V-B): forward anchors first; backward only where forward found nothing
-  run_direction(g, p, s, 0, active);
+  search_direction(g, p, s, 0, active);
   const bool need_back = active && s.best[t] == kNoKey;
-  if (wave_any(need_back)) run_direction(g, p, s, 1, need_back);
+  if (wave_any(need_back)) search_direction(g, p, s, 1, need_back);
 
   const unsigned long long key = active ? s.best[t] : kNoKey;
   const bool found = key != kNoKey;
