@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of HIP graph replays")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
+    ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
     return ap.parse_args()
 
 
@@ -89,17 +91,23 @@ def main():
     ws_find = torch.empty(max(256, L.compass_find_workspace_bytes(E, b.n_tracks)), dtype=torch.uint8, device=dev)
     ws_fg = torch.empty(L.compass_fit_grad_workspace_bytes(S), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_autotune:
+        c0 = copies[0]
+        tuned = utc.autotune(geom, params, E, c0["words"], c0["boff"], *c0["vel"], c0["vo"], reps=5)
+    lau_dec = tuned["decode"] if tuned else None
+    lau_find = tuned["find"] if tuned else None
 
     def step(c, ev=None):
         stream = torch.cuda.current_stream()
         if ev is not None:
             ev[0].record(stream)
         utc.ut_decode(geom, c["words"], c["boff"], E, hit_capacity=b.n_words, error_flags=flags,
-                      out=c["hits"], workspace=ws_dec)
+                      out=c["hits"], workspace=ws_dec, launch=lau_dec)
         if ev is not None:
             ev[1].record(stream)
         utc.compass_find(geom, params, E, c["hits"], *c["vel"], c["vo"], error_flags=flags,
-                         out=c["res"], workspace=ws_find)
+                         out=c["res"], workspace=ws_find, launch=lau_find)
         if ev is not None:
             ev[2].record(stream)
         utc.compass_fit_grad(geom, c["res"]["hit_idx"], c["hits"]["u"], c["hits"]["weight"],
@@ -163,6 +171,26 @@ def main():
     if int(flags.item()) != 0:
         raise RuntimeError(f"device error flags {int(flags.item())}")
 
+    # the same decode + Compass work launched one event at a time (eager), for comparison
+    per_event = None
+    if not args.no_per_event:
+        c = copies[0]
+        host_ho = c["hits"]["hit_offsets"].cpu().numpy().view(np.uint32).copy()
+        hits2 = {k: torch.empty_like(v) for k, v in c["hits"].items() if k != "error_flags"}
+        res2 = {k: torch.empty_like(v) for k, v in c["res"].items() if k != "error_flags"}
+        scratch = utc.api.per_event_loop(geom, params, E, c["words"], c["boff"], *c["vel"], c["vo"],
+                                         b.bank_offsets, host_ho, hits2, res2)
+        torch.cuda.synchronize()
+        pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pe0.record(stream)
+        utc.api.per_event_loop(geom, params, E, c["words"], c["boff"], *c["vel"], c["vo"],
+                               b.bank_offsets, host_ho, hits2, res2, scratch=scratch)
+        pe1.record(stream)
+        torch.cuda.synchronize()
+        pe_ms = pe0.elapsed_time(pe1)
+        per_event = {"events_per_s": round(E / (pe_ms * 1e-3), 1), "ms": round(pe_ms, 3),
+                     "what": "ut_decode + compass_find, one event per call, eager launches"}
+
     # algorithmic bytes (each input read once, each output written once)
     Nw, Nh, Nt = b.n_words, n_valid, b.n_tracks
     bytes_decode = 2 * Nw + 4 * (NB + 1) + 4 * (NB + 1) + 24 * Nh
@@ -201,6 +229,8 @@ def main():
         "fitted_tracks_per_s": round(n_found / (call_ms[2] * 1e-3), 1) if call_ms[2] > 0 else None,
         "decode_GBps": round(bytes_decode / (call_ms[0] * 1e-3) / 1e9, 1),
         "timing": "hip graph replay" if graphs is not None else "eager launches",
+        "launch": {"decode": lau_dec, "find": lau_find, "source": "autotuner" if tuned else "defaults"},
+        "batched_vs_per_event": per_event,
         "found_fraction": round(n_found / max(Nt, 1), 5),
         "wall_s": round(wall, 4),
     }

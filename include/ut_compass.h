@@ -155,6 +155,33 @@ utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks, const in
                             float* grad_offsets, void* workspace, size_t workspace_bytes,
                             hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Autotuning of the batched launch (not in the paper, which tuned its kernel parameters by hand,
+ * Section VI-C).  Each call runs the matching entry point on the caller's buffers (same arguments
+ * and meaning as ut_decode / compass_find) for every candidate launch shape: block in
+ * {64, 128, 256, 512} (decode) or {64, 128, 256} (Compass), grid in {one workgroup per work
+ * item, 256 .. 2048 persistent workgroups}; each shape runs once to warm up and then `reps` times
+ * (1..32).  *best receives the shape with the lowest median time, *best_us that time in
+ * microseconds.  Results do not depend on the shape.  Unlike the other calls these synchronise
+ * the stream (set-up calls); the outputs hold the last run's results.
+ * --------------------------------------------------------------------------------------------- */
+utc_status ut_decode_autotune(const utc_geometry* geom, const uint16_t* words,
+                              const uint32_t* bank_offsets, int32_t n_events, int64_t hit_capacity,
+                              uint32_t* hit_offsets, uint32_t* lhcbid, float* z, float* u,
+                              float* y_begin, float* y_end, float* weight, uint32_t* error_flags,
+                              void* workspace, size_t workspace_bytes, int32_t reps,
+                              utc_launch_config* best, float* best_us, hipStream_t stream);
+
+utc_status compass_find_autotune(const utc_geometry* geom, const utc_compass_params* params,
+                                 int32_t n_events, const uint32_t* hit_offsets, const float* hit_u,
+                                 const float* hit_weight, const float* hit_y_begin,
+                                 const float* hit_y_end, const float* vx, const float* vy,
+                                 const float* vtx, const float* vty, const uint32_t* velo_offsets,
+                                 int64_t n_tracks, int32_t* hit_idx, float* qop, float* chi2,
+                                 int32_t* nhits, uint32_t* error_flags, void* workspace,
+                                 size_t workspace_bytes, int32_t reps, utc_launch_config* best,
+                                 float* best_us, hipStream_t stream);
+
 /* Human-readable name of a status code. */
 const char* utc_status_string(int status);
 

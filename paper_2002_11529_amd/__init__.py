@@ -4,9 +4,9 @@ The computation lives in libutcompass.so (hand-written HIP, C ABI in include/ut_
 package is its thin ctypes binding.  See api.py.
 """
 from .api import (Geometry, compass_params, ut_decode, compass_find, compass_fit_grad,
-                  CompassChi2Function, library, version,
+                  CompassChi2Function, library, version, autotune,
                   FLAG_BANK_ORDER, FLAG_CAPACITY, FLAG_LAYER_OVERFLOW, FLAG_BANK_SIZE, MAX_BANK_WORDS)
 
 __all__ = ["Geometry", "compass_params", "ut_decode", "compass_find", "compass_fit_grad",
-           "CompassChi2Function", "library", "version", "FLAG_BANK_ORDER", "FLAG_CAPACITY",
+           "CompassChi2Function", "library", "version", "autotune", "FLAG_BANK_ORDER", "FLAG_CAPACITY",
            "FLAG_LAYER_OVERFLOW", "FLAG_BANK_SIZE", "MAX_BANK_WORDS"]

@@ -69,6 +69,12 @@ def library():
     L.compass_fit_grad.restype = ctypes.c_int
     L.compass_fit_grad.argtypes = [_P, _i64, _P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _f, _P,
                                    _P, _P, _P, _P, _sz, _P]
+    for name in ("ut_decode_autotune", "compass_find_autotune"):
+        getattr(L, name).restype = ctypes.c_int
+    L.ut_decode_autotune.argtypes = [_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                     _sz, _i32, _P, _P, _P]
+    L.compass_find_autotune.argtypes = [_P, _P, _i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        _i64, _P, _P, _P, _P, _P, _P, _sz, _i32, _P, _P, _P]
     L.utc_status_string.restype = ctypes.c_char_p
     L.utc_status_string.argtypes = [ctypes.c_int]
     L.utc_version.restype = ctypes.c_char_p
@@ -179,11 +185,11 @@ def ut_decode(geom: Geometry, words, bank_offsets, n_events: int, hit_capacity: 
 
 def compass_find(geom: Geometry, params, n_events: int, hits, vx, vy, vtx, vty, velo_offsets,
                  windows: bool = False, error_flags=None, launch=None, out=None, workspace=None,
-                 stream=None):
+                 stream=None, n_tracks=None):
     """Compass tracklet search for every VELO track.  Returns a dict of device tensors."""
     L = library()
     dev = vx.device
-    n = int(vx.shape[0])
+    n = int(vx.shape[0]) if n_tracks is None else int(n_tracks)
     if out is None:
         out = dict(hit_idx=torch.empty((n, 4), dtype=torch.int32, device=dev),
                    qop=torch.empty(n, dtype=torch.float32, device=dev),
@@ -265,6 +271,101 @@ class CompassChi2Function(torch.autograd.Function):
                              grad_scale=1.0, want_grad=True, want_chi2_track=False)
         g = grad_out.to(torch.float32)
         return r["grad_qop"] * g, r["grad_offsets"] * g, None, None
+
+
+def per_event_loop(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy, vtx, vty,
+                   velo_offsets, host_bank_offsets, host_hit_offsets, hits_out, res_out,
+                   scratch=None, stream=None):
+    """The same decode + Compass work launched one event at a time (the comparison baseline of
+    the batched launch).  Argument marshalling only: event e's banks are a slice of
+    bank_offsets (absolute word offsets), its hits go to hits_out at the event's first hit (taken
+    from host_hit_offsets of an earlier batched decode), its tracks' outputs to res_out at their
+    global positions.  Hit indices in res_out come out relative to the event's first hit."""
+    L = library()
+    dev = words.device
+    nb = 4 * geom.n_sectors
+    p = params if isinstance(params, UtcCompassParams) else compass_params(params)
+    if scratch is None:
+        scratch = dict(hoff=torch.empty(nb + 1, dtype=torch.int32, device=dev),
+                       wsd=_workspace(L.ut_decode_workspace_bytes(1, geom.n_sectors), dev),
+                       wsf=_workspace(L.compass_find_workspace_bytes(1, int(vx.shape[0])), dev),
+                       flags=torch.zeros(1, dtype=torch.int32, device=dev))
+    n_tracks = int(vx.shape[0])
+    for e in range(n_events):
+        base = int(host_hit_offsets[e * nb])
+        n_words = int(host_bank_offsets[(e + 1) * nb]) - int(host_bank_offsets[e * nb])
+        ev_hits = {k: hits_out[k][base:] for k in ("lhcbid", "z", "u", "y_begin", "y_end", "weight")}
+        ev_hits["hit_offsets"] = scratch["hoff"]
+        ut_decode(geom, words, bank_offsets[e * nb:(e + 1) * nb + 1], 1,
+                  hit_capacity=max(n_words, 0), error_flags=scratch["flags"], out=ev_hits,
+                  workspace=scratch["wsd"], stream=stream)
+        compass_find(geom, p, 1, ev_hits, vx, vy, vtx, vty, velo_offsets[e:e + 2],
+                     error_flags=scratch["flags"], out=res_out, workspace=scratch["wsf"],
+                     stream=stream, n_tracks=n_tracks)
+    return scratch
+
+
+def _cache_path():
+    return os.environ.get("UTC_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "utcompass", "autotune.json"))
+
+
+def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy, vtx, vty,
+             velo_offsets, reps: int = 5, use_cache: bool = True, stream=None):
+    """Pick the launch shapes of ut_decode and compass_find for this workload shape by timing them
+    in the library (ut_decode_autotune / compass_find_autotune).  The choice is cached as JSON,
+    keyed by GPU architecture and workload shape.  Returns dict(decode=..., find=..., *_us)."""
+    import json
+    L = library()
+    dev = words.device
+    arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
+    p = params if isinstance(params, UtcCompassParams) else compass_params(params)
+    n_tracks = int(vx.shape[0])
+    key = (f"{arch}|S={geom.n_sectors}|M={p.max_hits}|sec={p.n_sectors_search}|E={n_events}|"
+           f"Nw={int(words.shape[0]) >> 16}|Nt={n_tracks >> 10}")
+    path = _cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return cache[key]
+    hits = ut_decode(geom, words, bank_offsets, n_events, stream=stream)
+    ws = _workspace(L.ut_decode_workspace_bytes(n_events, geom.n_sectors), dev)
+    best, best_us = UtcLaunchConfig(), ctypes.c_float()
+    st = L.ut_decode_autotune(geom.ref, _ptr(words), _ptr(bank_offsets), n_events,
+                              int(words.shape[0]), _ptr(hits["hit_offsets"]), _ptr(hits["lhcbid"]),
+                              _ptr(hits["z"]), _ptr(hits["u"]), _ptr(hits["y_begin"]),
+                              _ptr(hits["y_end"]), _ptr(hits["weight"]), _ptr(hits["error_flags"]),
+                              _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(best_us),
+                              _stream(stream))
+    _check(st, "ut_decode_autotune")
+    dec = dict(block=best.block, grid=best.grid)
+    dec_us = float(best_us.value)
+    res = compass_find(geom, p, n_events, hits, vx, vy, vtx, vty, velo_offsets, stream=stream)
+    wsf = _workspace(L.compass_find_workspace_bytes(n_events, n_tracks), dev)
+    st = L.compass_find_autotune(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"]),
+                                 _ptr(hits["u"]), _ptr(hits["weight"]), _ptr(hits["y_begin"]),
+                                 _ptr(hits["y_end"]), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty),
+                                 _ptr(velo_offsets), n_tracks, _ptr(res["hit_idx"]), _ptr(res["qop"]),
+                                 _ptr(res["chi2"]), _ptr(res["nhits"]), _ptr(res["error_flags"]),
+                                 _ptr(wsf), wsf.numel(), reps, ctypes.byref(best),
+                                 ctypes.byref(best_us), _stream(stream))
+    _check(st, "compass_find_autotune")
+    out = dict(decode=dec, decode_us=dec_us, find=dict(block=best.block, grid=best.grid),
+               find_us=float(best_us.value))
+    if use_cache:
+        cache[key] = out
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + f".{os.getpid()}.tmp"
+            json.dump(cache, open(tmp, "w"), indent=1)
+            os.replace(tmp, path)
+        except OSError:
+            pass
+    return out
 
 
 def version() -> str:
