@@ -22,6 +22,46 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_OF_CALL = {"ut_decode": "k_decode", "compass_find": "k_compass", "compass_fit_grad": "k_fitgrad"}
+# sources each kernel is compiled from: counters taken before a change to any of them no longer apply
+KERNEL_SOURCES = {
+    "k_compass": ["paper_2002_11529_amd/csrc/compass.hip", "paper_2002_11529_amd/csrc/compass_group.hpp",
+                  "paper_2002_11529_amd/csrc/common.hpp", "include/ut_compass.h"],
+    "k_decode": ["paper_2002_11529_amd/csrc/decode.hip", "paper_2002_11529_amd/csrc/decode_unit.hpp",
+                 "paper_2002_11529_amd/csrc/common.hpp", "include/ut_compass.h"],
+    "k_fitgrad": ["paper_2002_11529_amd/csrc/fitgrad.hip", "paper_2002_11529_amd/csrc/common.hpp",
+                  "include/ut_compass.h"],
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary of the workload
+    (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain copy of known size), or
+    None when there is none or it was taken from other kernel sources than the current ones."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get(f"{kernel}.source_sha256_16") != kernel_source_hash(kernel):
+        return None
+    try:
+        return int(fields[f"{kernel}.hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -35,9 +75,13 @@ def parse():
                     help="input/output copies used round-robin so the working set exceeds the 256 MB Infinity Cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of HIP graph replays")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
+    ap.add_argument("--no-fitgrad", action="store_true",
+                    help="skip the fit-chi2 forward/backward figure on the 1e6-track workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -50,6 +94,10 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import synth
     import paper_2002_11529_amd as utc
@@ -221,12 +269,12 @@ def main():
                                f"{Nh} hits, {Nw} raw words",
                    "step": "ut_decode + compass_find + compass_fit_grad(fwd+bwd)",
                    "rotated_copies": R},
-        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload)},
         "calls_ms": {n: round(float(m), 5) for n, m in zip(names, call_ms)},
         "step_algorithmic_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
-        "fitted_tracks_per_s": round(n_found / (call_ms[2] * 1e-3), 1) if call_ms[2] > 0 else None,
         "decode_GBps": round(bytes_decode / (call_ms[0] * 1e-3) / 1e9, 1),
         "timing": "hip graph replay" if graphs is not None else "eager launches",
         "launch": {"decode": lau_dec, "find": lau_find, "source": "autotuner" if tuned else "defaults"},
@@ -234,29 +282,135 @@ def main():
         "found_fraction": round(n_found / max(Nt, 1), 5),
         "wall_s": round(wall, 4),
     }
+    if not args.no_fitgrad:
+        out["fitgrad"] = bench_fitgrad(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration():
+    """A plain copy of known size, for scaling the HBM byte counters (FETCH_SIZE, WRITE_SIZE)."""
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n, "bytes_written": n, "copies": 5}), flush=True)
+
+
+def bench_fitgrad(args, dev):
+    """Fit-chi2 forward + backward over the frozen tracks of the differentiation workload (21000
+    events, about 1.05e6 tracks with 3 or 4 hits), against the same calls launched per event."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2002_11529_amd as utc
+
+    b = synth.generate("fitgrad", with_truth=False)
+    S = b.detector.n_sectors
+    geom = utc.Geometry(b.detector, dev)
+    words = torch.from_numpy(b.words.view(np.int16).copy()).to(dev)
+    boff = torch.from_numpy(b.bank_offsets.view(np.int32).copy()).to(dev)
+    vel = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (b.velo_x, b.velo_y, b.velo_tx, b.velo_ty)]
+    vo = torch.from_numpy(b.velo_offsets.view(np.int32).copy()).to(dev)
+    hits = utc.ut_decode(geom, words, boff, b.n_events)
+    res = utc.compass_find(geom, b.params, b.n_events, hits, *vel, vo)
+    keep = res["nhits"] >= 3
+    idx = res["hit_idx"][keep].contiguous()
+    st = [v[keep].contiguous() for v in vel]
+    qop = res["qop"][keep].contiguous()
+    off = torch.zeros(4 * S, dtype=torch.float32, device=dev)
+    n = int(qop.shape[0])
+    ws = torch.empty(utc.library().compass_fit_grad_workspace_bytes(S), dtype=torch.uint8, device=dev)
+    out = dict(chi2_total=torch.empty(1, dtype=torch.float64, device=dev),
+               chi2_track=torch.empty(n, dtype=torch.float32, device=dev),
+               grad_qop=torch.empty(n, dtype=torch.float32, device=dev),
+               grad_offsets=torch.empty(4 * S, dtype=torch.float32, device=dev))
+    fwd_out = dict(chi2_total=out["chi2_total"], chi2_track=out["chi2_track"])
+
+    def call(o, grad):
+        utc.compass_fit_grad(geom, idx, hits["u"], hits["weight"], hits["lhcbid"], *st, qop, off,
+                             want_grad=grad, out=o, workspace=ws)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_fb = timed(lambda: call(out, True), args.steps)
+    ms_f = timed(lambda: call(fwd_out, False), args.steps)
+    # the same work, one call per event
+    ev_of_track = np.repeat(np.arange(b.n_events), np.diff(b.velo_offsets.astype(np.int64)))
+    kept_per_event = np.bincount(ev_of_track[keep.cpu().numpy()], minlength=b.n_events)
+    ko = np.zeros(b.n_events + 1, dtype=np.int64)
+    np.cumsum(kept_per_event, out=ko[1:])
+    rows = [(int(ko[e]), int(ko[e + 1])) for e in range(b.n_events) if ko[e + 1] > ko[e]]
+
+    def per_event():
+        for t0, t1 in rows:
+            o = dict(chi2_total=out["chi2_total"], chi2_track=out["chi2_track"][t0:t1],
+                     grad_qop=out["grad_qop"][t0:t1], grad_offsets=out["grad_offsets"])
+            utc.compass_fit_grad(geom, idx[t0:t1], hits["u"], hits["weight"], hits["lhcbid"],
+                                 *(v[t0:t1] for v in st), qop[t0:t1], off, out=o, workspace=ws)
+
+    ms_pe = timed(per_event, 1) if not args.no_per_event else None
+    n_hits = int((idx >= 0).sum().item())
+    bytes_fb = n * (16 + 16 + 4 + 8) + n_hits * 12 + 2 * 4 * (4 * S)
+    return {"workload": f"fitgrad: {b.n_events} events, {n} frozen tracks, {n_hits} hits, {S} sectors/layer",
+            "fwd_bwd_tracks_per_s": round(n / (ms_fb * 1e-3), 1), "fwd_bwd_ms": round(ms_fb, 5),
+            "fwd_only_tracks_per_s": round(n / (ms_f * 1e-3), 1), "fwd_only_ms": round(ms_f, 5),
+            "fwd_bwd_algorithmic_GBps": round(bytes_fb / (ms_fb * 1e-3) / 1e9, 1),
+            "per_event_launch_tracks_per_s": round(n / (ms_pe * 1e-3), 1) if ms_pe else None,
+            "per_event_launch_ms": round(ms_pe, 3) if ms_pe else None,
+            "per_event_what": "compass_fit_grad fwd+bwd, one call per event (the offset gradient of "
+                              "each call overwrites the last; no cross-event sum)"}
+
+
 def cpu_baseline(b, seconds):
-    """The oracle (single thread) on the same events, repeated until about `seconds` elapse."""
+    """The oracle (single thread) on a bounded sample of the same events: the first m events, m
+    chosen so that one pass takes about a second, passes repeated until about `seconds` elapse."""
     import numpy as np
     import oracle
-    reps, t = 0, 0.0
-    t0 = time.perf_counter()
-    while t < seconds and reps < 50:
-        d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
-        c = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx,
-                           b.velo_ty, b.velo_offsets)
-        oracle.fit_grad(b.detector, c["hit_idx"], d["u"], d["weight"], d["lhcbid"], b.velo_x, b.velo_y,
-                        b.velo_tx, b.velo_ty, c["qop"], np.zeros(4 * b.detector.n_sectors, np.float32))
+    import synth
+
+    def one_pass(sub):
+        d = oracle.decode(sub.detector, sub.words, sub.bank_offsets, sub.n_events)
+        c = oracle.compass(sub.detector, sub.params, sub.n_events, d, sub.velo_x, sub.velo_y,
+                           sub.velo_tx, sub.velo_ty, sub.velo_offsets)
+        oracle.fit_grad(sub.detector, c["hit_idx"], d["u"], d["weight"], d["lhcbid"], sub.velo_x,
+                        sub.velo_y, sub.velo_tx, sub.velo_ty, c["qop"],
+                        np.zeros(4 * sub.detector.n_sectors, np.float32))
+
+    m = min(b.n_events, 20)
+    while True:
+        sub = synth.take_events(b, np.arange(m)) if m < b.n_events else b
+        t0 = time.perf_counter()
+        one_pass(sub)
+        dt = time.perf_counter() - t0
+        if m == b.n_events or dt >= 0.5:
+            break
+        m = min(b.n_events, max(m + 1, int(m * 1.0 / max(dt, 1e-3))))
+    reps, t = 1, dt
+    t0 = time.perf_counter() - dt
+    while t < seconds:
+        one_pass(sub)
         reps += 1
         t = time.perf_counter() - t0
-    return {"value": round(reps * b.n_events / t, 1), "unit": "events/s", "cores": 1,
+    return {"value": round(reps * sub.n_events / t, 1), "unit": "events/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{reps} passes over the {b.n_events}-event batch (decode + Compass + fit-chi2 "
-                      f"fwd+bwd), single thread, {t:.1f} s"}
+            "sample": f"{reps} passes over the first {sub.n_events} of the {b.n_events} events "
+                      f"(decode + Compass + fit-chi2 fwd+bwd), single thread, {t:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -6,7 +6,7 @@ no tracklet finding, no fit.  Random numbers come from ``numpy.random.default_rn
 so every consumer sees the same bytes for the same (config, seed).
 """
 from .detector import Detector, make_detector, CompassParams, make_compass_params
-from .events import EventBatch, generate, CONFIGS, config
+from .events import EventBatch, generate, take_events, CONFIGS, config
 
 __all__ = ["Detector", "make_detector", "CompassParams", "make_compass_params",
-           "EventBatch", "generate", "CONFIGS", "config"]
+           "EventBatch", "generate", "take_events", "CONFIGS", "config"]

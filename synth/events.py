@@ -17,6 +17,8 @@ Event model (a stand-in for the LHCb minbias samples, which are not available):
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -66,7 +68,7 @@ class EventBatch:
         return int(np.count_nonzero(self.words & 0xF))
 
 
-# Workload recipes (see the design doc for the reasoning behind each number).
+# Workload recipes: sizes and distributions of the synthetic stand-ins for the paper's samples.
 CONFIGS = {
     "tiny": dict(n_sectors=32, n_events=100, seed=1, tracks=("fixed", 50),
                  noise=("fixed", 200), hidden=("none",), p_min=1500.0, max_hits=8),
@@ -120,12 +122,112 @@ def _particles(rng, n):
     return x, y, tx, ty, q / p
 
 
+CHUNK_EVENTS = 1024   # events are drawn in blocks with a random stream of their own
+
+
+def _chunk(rng, det, E, S, tracks, noise, hidden, delta_true, extra_padding_prob, with_truth):
+    """Draw E events; event indices and track ids are local to the block."""
+    L = N_LAYERS
+    n_velo = _counts(rng, tracks, E)
+    n_hidden = _counts(rng, hidden, E, base=n_velo)
+    n_noise = _counts(rng, noise, E)
+
+    # particles: VELO tracks (in event order) then hidden particles (in event order)
+    Nv, Nh = int(n_velo.sum()), int(n_hidden.sum())
+    vx, vy, vtx, vty, vqop = _particles(rng, Nv)
+    hx, hy, htx, hty, hqop = _particles(rng, Nh)
+    px = np.concatenate([vx, hx]).astype(np.float64)
+    py = np.concatenate([vy, hy]).astype(np.float64)
+    ptx = np.concatenate([vtx, htx]).astype(np.float64)
+    pty = np.concatenate([vty, hty]).astype(np.float64)
+    pqop = np.concatenate([vqop, hqop])
+    pev = np.concatenate([np.repeat(np.arange(E, dtype=np.int32), n_velo),
+                          np.repeat(np.arange(E, dtype=np.int32), n_hidden)])
+    NP = Nv + Nh
+
+    # particle x layer crossings
+    dz = det.z_layer.astype(np.float64) - np.float64(det.z_velo)
+    dxdy = det.dxdy.astype(np.float64)
+    a = det.a_kick.astype(np.float64)
+    eff = rng.random((NP, L)) < HIT_EFFICIENCY
+    smear = rng.normal(0.0, SIGMA0_MM, (NP, L))
+    y = py[:, None] + pty[:, None] * dz[None, :]
+    u_meas = px[:, None] + ptx[:, None] * dz[None, :] + pqop[:, None] * a[None, :]
+    u_meas -= y * dxdy[None, :]
+    u_meas += smear
+    del smear
+    if delta_true is not None:
+        sec_f = np.floor((u_meas - det.u_min_f64) / SECTOR_WIDTH_MM)
+        sidx = np.clip(sec_f, 0, S - 1).astype(np.int64) + (np.arange(L) * S)[None, :]
+        u_meas += delta_true[sidx].astype(np.float64)
+    keep = eff & (np.abs(y) <= Y_HALF_MM)
+    pos = u_meas - det.u_min_f64
+    sec = np.floor(pos / SECTOR_WIDTH_MM)
+    keep &= (sec >= 0) & (sec < S)
+    pi, li = np.nonzero(keep)
+    t_sec = sec[pi, li].astype(np.int32)
+    within = pos[pi, li] - t_sec * SECTOR_WIDTH_MM
+    t_q = np.clip(np.floor(within / (PITCH_MM / 8.0)), 0, 4095).astype(np.int32)
+    n_layers_hit = np.bincount(pi[pi < Nv], minlength=Nv).astype(np.int8)
+
+    # noise
+    NN = int(n_noise.sum())
+    n_layer = rng.integers(0, L, NN, dtype=np.int32)
+    n_sec = rng.integers(0, S, NN, dtype=np.int32)
+    n_q = rng.integers(0, 4096, NN, dtype=np.int32)
+
+    ev = np.concatenate([pev[pi], np.repeat(np.arange(E, dtype=np.int32), n_noise)])
+    layer = np.concatenate([li.astype(np.int32), n_layer])
+    sector = np.concatenate([t_sec, n_sec])
+    qv = np.concatenate([t_q, n_q])
+    NHIT = ev.shape[0]
+    size = (1 + np.searchsorted(np.cumsum(SIZE_PROBS), rng.random(NHIT), side="right")).astype(np.int32)
+    size = np.minimum(size, 3)
+    bank = (ev.astype(np.int64) * L + layer) * S + sector
+    words = ((qv >> 3) << 7) | ((qv & 7) << 4) | size
+
+    # padding words: one per odd bank (32-bit alignment) plus optional random extra pairs
+    NB = E * L * S
+    counts = np.bincount(bank, minlength=NB)
+    pad_banks = np.nonzero(counts & 1)[0]
+    if extra_padding_prob > 0:
+        extra = np.nonzero(rng.random(NB) < extra_padding_prob)[0]
+        pad_banks = np.concatenate([pad_banks, extra, extra])
+    NPAD = pad_banks.shape[0]
+    bank = np.concatenate([bank, pad_banks])
+    words = np.concatenate([words, np.zeros(NPAD, dtype=np.int32)])
+
+    # shuffle inside banks: sort by (bank, random 24-bit key); quicksort is deterministic for a
+    # given input and much faster than a stable multi-key sort
+    order = np.argsort((bank << 24) | rng.integers(0, 1 << 24, bank.shape[0]))
+    counts += np.bincount(pad_banks, minlength=NB)
+    out = dict(words=words[order].astype(np.uint16), bank_counts=counts, n_velo=n_velo,
+               vx=vx, vy=vy, vtx=vtx, vty=vty, vqop=vqop, n_layers_hit=n_layers_hit)
+    if with_truth:
+        ptruth = np.concatenate([np.arange(Nv, dtype=np.int64), np.full(Nh, TRUTH_HIDDEN, np.int64)])
+        truth_id = np.concatenate([ptruth[pi], np.full(NN, TRUTH_NOISE, np.int64),
+                                   np.full(NPAD, TRUTH_PADDING, np.int64)])
+        umeas = np.concatenate([u_meas[pi, li], np.full(NN + NPAD, np.nan)])
+        layer = np.concatenate([layer, ((pad_banks // S) % L).astype(np.int32)])
+        sector = np.concatenate([sector, (pad_banks % S).astype(np.int32)])
+        qv = np.concatenate([qv, np.zeros(NPAD, dtype=np.int32)])
+        size = np.concatenate([size, np.zeros(NPAD, dtype=np.int32)])
+        out["truth"] = dict(track=truth_id[order], u_meas=umeas[order],
+                            layer=layer[order].astype(np.int8), sector=sector[order].astype(np.int32),
+                            q=qv[order].astype(np.int16), size=size[order].astype(np.int8),
+                            n_hidden=n_hidden, n_noise=n_noise)
+    return out
+
+
 def generate(name: str = "tiny", n_events: Optional[int] = None, seed: Optional[int] = None, *,
              with_truth: bool = True, n_sectors: Optional[int] = None,
              max_hits: Optional[int] = None, n_sectors_search: int = 5,
              tracks=None, noise=None, hidden=None, misalign_sigma: Optional[float] = None,
              extra_padding_prob: float = 0.0) -> EventBatch:
-    """Generate a batch for recipe `name`; keyword arguments override the recipe."""
+    """Generate a batch for recipe `name`; keyword arguments override the recipe.
+
+    Events are drawn in blocks of CHUNK_EVENTS, block c from the stream default_rng([seed, c]);
+    the per-sector offsets (when the recipe has them) come from default_rng([seed, 1 << 20])."""
     cfg = config(name)
     n_events = cfg["n_events"] if n_events is None else int(n_events)
     seed = cfg["seed"] if seed is None else int(seed)
@@ -138,116 +240,82 @@ def generate(name: str = "tiny", n_events: Optional[int] = None, seed: Optional[
     params = make_compass_params(p_min_mev=cfg["p_min"],
                                  max_hits=cfg["max_hits"] if max_hits is None else max_hits,
                                  n_sectors_search=n_sectors_search)
-    rng = np.random.default_rng(seed)
-    E, L = n_events, N_LAYERS
-
-    n_velo = _counts(rng, tracks, E)
-    n_hidden = _counts(rng, hidden, E, base=n_velo)
-    n_noise = _counts(rng, noise, E)
+    L, E = N_LAYERS, n_events
     delta_true = None
     if misalign_sigma and misalign_sigma > 0:
-        delta_true = rng.normal(0.0, misalign_sigma, L * S).astype(np.float32)
+        delta_true = np.random.default_rng([seed, 1 << 20]).normal(
+            0.0, misalign_sigma, L * S).astype(np.float32)
 
-    # particles: VELO tracks (in event order) then hidden particles (in event order)
-    Nv, Nh = int(n_velo.sum()), int(n_hidden.sum())
-    vx, vy, vtx, vty, vqop = _particles(rng, Nv)
-    hx, hy, htx, hty, hqop = _particles(rng, Nh)
-    ev_v = np.repeat(np.arange(E, dtype=np.int64), n_velo)
-    ev_h = np.repeat(np.arange(E, dtype=np.int64), n_hidden)
-    px = np.concatenate([vx, hx]).astype(np.float64)
-    py = np.concatenate([vy, hy]).astype(np.float64)
-    ptx = np.concatenate([vtx, htx]).astype(np.float64)
-    pty = np.concatenate([vty, hty]).astype(np.float64)
-    pqop = np.concatenate([vqop, hqop])
-    pev = np.concatenate([ev_v, ev_h])
-    ptruth = np.concatenate([np.arange(Nv, dtype=np.int64),
-                             np.full(Nh, TRUTH_HIDDEN, dtype=np.int64)])
-    NP = Nv + Nh
+    def block(c):
+        e0 = c * CHUNK_EVENTS
+        return _chunk(np.random.default_rng([seed, c]), det, min(CHUNK_EVENTS, E - e0), S,
+                      tracks, noise, hidden, delta_true, extra_padding_prob, with_truth)
 
-    # particle x layer crossings
-    z = det.z_layer.astype(np.float64)
-    dz = z - np.float64(det.z_velo)
-    dxdy = det.dxdy.astype(np.float64)
-    a = det.a_kick.astype(np.float64)
-    eff = rng.random((NP, L)) < HIT_EFFICIENCY
-    smear = rng.normal(0.0, SIGMA0_MM, (NP, L))
-    x = px[:, None] + ptx[:, None] * dz[None, :] + pqop[:, None] * a[None, :]
-    y = py[:, None] + pty[:, None] * dz[None, :]
-    u_exact = x - y * dxdy[None, :]
-    u_meas = u_exact + smear
-    sec_f = np.floor((u_meas - det.u_min_f64) / SECTOR_WIDTH_MM)
-    if delta_true is not None:
-        sidx = np.clip(sec_f, 0, S - 1).astype(np.int64) + (np.arange(L) * S)[None, :]
-        u_meas = u_meas + delta_true[sidx].astype(np.float64)
-    keep = eff & (np.abs(y) <= Y_HALF_MM)
-    pos = u_meas - det.u_min_f64
-    sec = np.floor(pos / SECTOR_WIDTH_MM)
-    keep &= (sec >= 0) & (sec < S)
-    pi, li = np.nonzero(keep)
-    t_sec = sec[pi, li].astype(np.int64)
-    within = pos[pi, li] - t_sec * SECTOR_WIDTH_MM
-    t_q = np.clip(np.floor(within / (PITCH_MM / 8.0)), 0, 4095).astype(np.int64)
-    t_ev = pev[pi]
-    t_layer = li.astype(np.int64)
-    t_truth = ptruth[pi]
-    t_umeas = u_meas[pi, li]
-    n_layers_hit = np.zeros(Nv, dtype=np.int8)
-    np.add.at(n_layers_hit, pi[pi < Nv], 1)
+    n_blocks = (E + CHUNK_EVENTS - 1) // CHUNK_EVENTS
+    if n_blocks > 1:   # blocks are independent; numpy releases the GIL in the heavy steps
+        with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1, n_blocks)) as pool:
+            parts = list(pool.map(block, range(n_blocks)))
+    else:
+        parts = [block(c) for c in range(n_blocks)]
 
-    # noise
-    NN = int(n_noise.sum())
-    n_ev = np.repeat(np.arange(E, dtype=np.int64), n_noise)
-    n_layer = rng.integers(0, L, NN)
-    n_sec = rng.integers(0, S, NN)
-    n_q = rng.integers(0, 4096, NN)
+    def cat(key, dtype=None):
+        if not parts:
+            return np.zeros(0, dtype=dtype)
+        return np.concatenate([p[key] for p in parts]).astype(dtype, copy=False) if dtype else \
+            np.concatenate([p[key] for p in parts])
 
-    ev = np.concatenate([t_ev, n_ev])
-    layer = np.concatenate([t_layer, n_layer])
-    sector = np.concatenate([t_sec, n_sec])
-    qv = np.concatenate([t_q, n_q])
-    truth_id = np.concatenate([t_truth, np.full(NN, TRUTH_NOISE, dtype=np.int64)])
-    umeas = np.concatenate([t_umeas, np.full(NN, np.nan)])
-    NHIT = ev.shape[0]
-    size = (1 + np.searchsorted(np.cumsum(SIZE_PROBS), rng.random(NHIT), side="right")).astype(np.int64)
-    size = np.minimum(size, 3)
-    bank = (ev * L + layer) * S + sector
-    words = ((qv >> 3) << 7) | ((qv & 7) << 4) | size
-
-    # padding words: one per odd bank (32-bit alignment) plus optional random extras
-    NB = E * L * S
-    counts = np.bincount(bank, minlength=NB)
-    pad_banks = np.nonzero(counts & 1)[0]
-    if extra_padding_prob > 0:
-        extra = np.nonzero(rng.random(NB) < extra_padding_prob)[0]
-        pad_banks = np.concatenate([pad_banks, extra, extra])   # two words keep the parity
-    NPAD = pad_banks.shape[0]
-    bank = np.concatenate([bank, pad_banks])
-    words = np.concatenate([words, np.zeros(NPAD, dtype=np.int64)])
-    truth_id = np.concatenate([truth_id, np.full(NPAD, TRUTH_PADDING, dtype=np.int64)])
-    umeas = np.concatenate([umeas, np.full(NPAD, np.nan)])
-    layer = np.concatenate([layer, (pad_banks // S) % L])
-    sector = np.concatenate([sector, pad_banks % S])
-    qv = np.concatenate([qv, np.zeros(NPAD, dtype=np.int64)])
-    size = np.concatenate([size, np.zeros(NPAD, dtype=np.int64)])
-
-    # shuffle inside banks: sort by (bank, random 24-bit key); quicksort is deterministic for a
-    # given input and much faster than a stable multi-key sort
-    shuffle_key = (bank << 24) | rng.integers(0, 1 << 24, bank.shape[0])
-    order = np.argsort(shuffle_key)
-    counts = np.bincount(bank, minlength=NB)
-    bank_offsets = np.zeros(NB + 1, dtype=np.uint32)
+    words = cat("words", np.uint16)
+    counts = cat("bank_counts", np.int64)
+    bank_offsets = np.zeros(E * L * S + 1, dtype=np.uint32)
     np.cumsum(counts, out=bank_offsets[1:])
-
+    n_velo = cat("n_velo", np.int64)
     velo_offsets = np.zeros(E + 1, dtype=np.uint32)
     np.cumsum(n_velo, out=velo_offsets[1:])
     batch = EventBatch(
         name=name, seed=seed, detector=det, params=params, n_events=E,
-        words=words[order].astype(np.uint16), bank_offsets=bank_offsets,
-        velo_x=vx, velo_y=vy, velo_tx=vtx, velo_ty=vty, velo_offsets=velo_offsets,
-        qop_true=vqop, n_layers_hit=n_layers_hit, delta_true=delta_true)
+        words=words, bank_offsets=bank_offsets,
+        velo_x=cat("vx", np.float32), velo_y=cat("vy", np.float32), velo_tx=cat("vtx", np.float32),
+        velo_ty=cat("vty", np.float32), velo_offsets=velo_offsets,
+        qop_true=cat("vqop", np.float64), n_layers_hit=cat("n_layers_hit", np.int8),
+        delta_true=delta_true)
     if with_truth:
-        batch.truth = dict(track=truth_id[order].astype(np.int32), u_meas=umeas[order],
-                           layer=layer[order].astype(np.int8), sector=sector[order].astype(np.int32),
-                           q=qv[order].astype(np.int16), size=size[order].astype(np.int8),
-                           n_hidden=n_hidden, n_noise=n_noise)
+        tr = {}
+        toff = 0
+        tracks_ids = []
+        for p in parts:
+            t = p["truth"]["track"]
+            tracks_ids.append(np.where(t >= 0, t + toff, t))
+            toff += int(p["n_velo"].sum())
+        tr["track"] = np.concatenate(tracks_ids).astype(np.int32) if parts else np.zeros(0, np.int32)
+        for k in ("u_meas", "layer", "sector", "q", "size", "n_hidden", "n_noise"):
+            tr[k] = np.concatenate([p["truth"][k] for p in parts]) if parts else np.zeros(0)
+        batch.truth = tr
     return batch
+
+
+def take_events(batch: EventBatch, events) -> EventBatch:
+    """A new batch holding the given events (in the given order) of `batch`: their raw banks with
+    rebased bank offsets and their VELO states.  Truth is not carried over."""
+    ev = np.asarray(events, dtype=np.int64)
+    L, S = N_LAYERS, batch.detector.n_sectors
+    nb = L * S
+    bo = batch.bank_offsets.astype(np.int64)
+    vo = batch.velo_offsets.astype(np.int64)
+    words, counts, tsel = [], [], []
+    for e in ev:
+        words.append(batch.words[bo[e * nb]:bo[(e + 1) * nb]])
+        counts.append(np.diff(bo[e * nb:(e + 1) * nb + 1]))
+        tsel.append(np.arange(vo[e], vo[e + 1]))
+    tsel = np.concatenate(tsel) if tsel else np.zeros(0, np.int64)
+    bank_offsets = np.zeros(ev.shape[0] * nb + 1, dtype=np.uint32)
+    if counts:
+        np.cumsum(np.concatenate(counts), out=bank_offsets[1:])
+    velo_offsets = np.zeros(ev.shape[0] + 1, dtype=np.uint32)
+    np.cumsum(vo[ev + 1] - vo[ev], out=velo_offsets[1:])
+    return EventBatch(
+        name=batch.name, seed=batch.seed, detector=batch.detector, params=batch.params,
+        n_events=int(ev.shape[0]),
+        words=np.concatenate(words) if words else np.zeros(0, np.uint16), bank_offsets=bank_offsets,
+        velo_x=batch.velo_x[tsel], velo_y=batch.velo_y[tsel], velo_tx=batch.velo_tx[tsel],
+        velo_ty=batch.velo_ty[tsel], velo_offsets=velo_offsets, qop_true=batch.qop_true[tsel],
+        n_layers_hit=batch.n_layers_hit[tsel], delta_true=batch.delta_true)

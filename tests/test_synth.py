@@ -73,3 +73,22 @@ def test_detector_description():
     assert abs(0.5 * (float(det.a_kick[1]) + float(det.a_kick[2])) - 1200.0) < 1e-3
     with pytest.raises(ValueError):
         synth.make_detector(31)
+
+
+def test_take_events_matches_slices():
+    import oracle
+    b = synth.generate("tiny", n_events=6, seed=9)
+    sub = synth.take_events(b, [4, 1])
+    S = b.detector.n_sectors
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    ds = oracle.decode(sub.detector, sub.words, sub.bank_offsets, sub.n_events)
+    for k, e in enumerate((4, 1)):
+        ho = d["hit_offsets"].astype(np.int64)
+        a0, a1 = ho[e * 4 * S], ho[(e + 1) * 4 * S]
+        s0 = ds["hit_offsets"][k * 4 * S]
+        assert np.array_equal(ds["hit_offsets"][k * 4 * S:(k + 1) * 4 * S + 1] - s0,
+                              (ho[e * 4 * S:(e + 1) * 4 * S + 1] - a0).astype(np.uint32))
+        assert np.array_equal(ds["u"][s0:s0 + a1 - a0], d["u"][a0:a1])
+        t0, t1 = b.velo_offsets[e], b.velo_offsets[e + 1]
+        u0, u1 = sub.velo_offsets[k], sub.velo_offsets[k + 1]
+        assert np.array_equal(sub.velo_tx[u0:u1], b.velo_tx[t0:t1])
