@@ -4,11 +4,13 @@
 // they fit, the u of its hits are staged in LDS; then each wavefront runs the search for groups of
 // 16 VELO tracks (compass_group.hpp): windows by binary search over the staged hits, tracklets by
 // anchor pairs spread over the lanes, selection by an LDS atomic minimum of a total-order key.
+#include <cmath>
+
 #include "compass_group.hpp"
 
 namespace utc {
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
           const float* __restrict__ hu, const float* __restrict__ hw,
           const float* __restrict__ hyb, const float* __restrict__ hye,
@@ -135,6 +137,12 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   p.half = (params->n_sectors_search - 1) / 2;
   p.slope_tol = params->slope_tol;
   p.eps = params->completion_tol;
+  // the pruning bound needs positive kick factors and non-negative finite weights
+  p.prune = 1;
+  for (int l = 0; l < kLayers; ++l)
+    if (!(geom->a_kick[l] > 0.0f) || !std::isfinite(geom->a_kick[l])) p.prune = 0;
+  for (int i = 0; i < 16; ++i)
+    if (!(geom->weight_by_size[i] >= 0.0f) || !std::isfinite(geom->weight_by_size[i])) p.prune = 0;
   const int block = launch ? launch->block : 256;
   const int waves = block / kWave;
   // stage u of events up to u_cap hits, keeping the workgroup's LDS at or under 40 KiB so that

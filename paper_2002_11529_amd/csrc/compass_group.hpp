@@ -23,6 +23,7 @@ struct CPar {
   int half;           // (n_sectors_search - 1) / 2
   float slope_tol;
   float eps;          // completion interval margin (mm)
+  int prune;          // lower-bound pruning of 4-hit candidates allowed (kick factors > 0, weights >= 0)
 };
 
 // Hits of the current event as seen by the search.  kULds / kWLds: u / weight read from LDS
@@ -62,6 +63,8 @@ struct GroupScratch {
   float* tx;          // [16] VELO slope tx of each track
   int32_t* nwin;      // [64] window sizes
   unsigned long long* best;  // [16] selection key minimum
+  unsigned long long* lbk;   // [16] seed choice of the batch: two-anchor bound << 32 | lane
+  uint32_t* umask;    // [64] usable window slots (strip covers the track's y)
   uint32_t* poff;     // [17] pair offsets of the tracks
   uint32_t* bp;       // [64] batch of anchor pairs that passed the slope test: t | jA<<8 | jB<<16
   uint32_t* bm1;      // [64] their completion masks in layer C1
@@ -70,7 +73,7 @@ struct GroupScratch {
 };
 
 __host__ __device__ inline size_t group_scratch_bytes(int max_hits) {
-  const size_t b = 8 * kGroupTracks + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
+  const size_t b = 16 * kGroupTracks + 4 * 64 + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
                    4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65;
   return (b + 15) / 16 * 16;
 }
@@ -78,7 +81,9 @@ __host__ __device__ inline size_t group_scratch_bytes(int max_hits) {
 __device__ inline GroupScratch carve_group(char* p, int max_hits) {
   GroupScratch s;
   s.best = reinterpret_cast<unsigned long long*>(p);
-  s.tm = reinterpret_cast<float*>(s.best + kGroupTracks);
+  s.lbk = s.best + kGroupTracks;
+  s.umask = reinterpret_cast<uint32_t*>(s.lbk + kGroupTracks);
+  s.tm = reinterpret_cast<float*>(s.umask + 64);
   s.tw = s.tm + 64 * max_hits;
   s.xs = s.tw + 64 * max_hits;
   s.tx = s.xs + 64;
@@ -142,125 +147,280 @@ __device__ inline uint32_t nth_set_bit(uint32_t m, uint32_t n) {
   return (uint32_t)__builtin_ctz(m);
 }
 
-// Anchor pair of a direction: slope of the two anchor hits and whether it passes the slope test.
-__device__ inline bool pair_slope(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
-                                  int B, int jA, int jB, float& mA, float& slope) {
-  const int oA = tile_at(t, A, jA), oB = tile_at(t, B, jB);
-  if (s.tw[oA] < 0.0f || s.tw[oB] < 0.0f) return false;
-  mA = s.tm[oA];
-  const float mB = s.tm[oB];
-  const float inv_dz_ab = 1.0f / (g.z_layer[B] - g.z_layer[A]);
-  slope = (mB - mA) * inv_dz_ab;
-  return fabsf(slope - s.tx[t]) <= p.slope_tol;
+// Bit mask of the window slots [lo, hi) (0 <= lo, hi <= 32).
+__device__ inline uint32_t range_mask(uint32_t lo, uint32_t hi) {
+  if (hi <= lo) return 0u;
+  const uint32_t up = hi >= 32u ? ~0u : ((1u << hi) - 1u);
+  return up & ~((1u << lo) - 1u);
 }
 
-// Completion hits of a passing pair in layer Cl: inside the interval spanned by the pair-slope and
-// VELO-slope extrapolations from the first anchor, widened by the completion tolerance.
-__device__ inline uint32_t completion_mask(const Geom& g, const CPar& p, const GroupScratch& s,
-                                           int t, int A, int Cl, float mA, float slope) {
+// Window slots hold the hits in ascending u, so their x at the track's y (u plus one constant,
+// rounded) is non-decreasing, and every test of the search that compares a monotone function of
+// that x with bounds selects a contiguous slot range; the ranges are found by binary search with
+// the test itself as predicate, so they contain exactly the slots the test accepts.
+
+// Anchor-B slots that pass the slope test with anchor-A hit mA: |(mB - mA)/dz - tx| <= slope_tol,
+// evaluated as (mB - mA) * (1/dz) - tx in binary32.  The deviation is monotone in mB (decreasing
+// when dz < 0, i.e. in the backward direction).
+__device__ inline uint32_t slope_range(const GroupScratch& s, int t, int B, float mA, float inv_dz,
+                                       float tx, float tol) {
+  const uint32_t n = (uint32_t)s.nwin[t * 4 + B];
+  auto dev = [&](uint32_t j) { return (s.tm[tile_at(t, B, (int)j)] - mA) * inv_dz - tx; };
+  uint32_t lo, hi;
+  if (inv_dz >= 0.0f) {
+    lo = first_true_u32(0u, n, [&](uint32_t j) { return dev(j) >= -tol; });
+    hi = first_true_u32(lo, n, [&](uint32_t j) { return dev(j) > tol; });
+  } else {
+    lo = first_true_u32(0u, n, [&](uint32_t j) { return dev(j) <= tol; });
+    hi = first_true_u32(lo, n, [&](uint32_t j) { return dev(j) < -tol; });
+  }
+  return range_mask(lo, hi);
+}
+
+// Completion slots of a passing pair in layer Cl: x inside the interval spanned by the pair-slope
+// and VELO-slope extrapolations from the first anchor, widened by the completion tolerance.
+__device__ inline uint32_t completion_range(const Geom& g, const CPar& p, const GroupScratch& s,
+                                            int t, int A, int Cl, float mA, float slope) {
   const float d = g.z_layer[Cl] - g.z_layer[A];
   const float xt = mA + slope * d;
   const float xv = mA + s.tx[t] * d;
   const float lo = fminf(xt, xv) - p.eps;
   const float hi = fmaxf(xt, xv) + p.eps;
-  uint32_t mk = 0;
-  const int n = s.nwin[t * 4 + Cl];
-  for (int j = 0; j < n; ++j) {
-    const int o = tile_at(t, Cl, j);
-    const float m = s.tm[o];
-    if (s.tw[o] >= 0.0f && lo <= m && m <= hi) mk |= 1u << j;
+  const uint32_t n = (uint32_t)s.nwin[t * 4 + Cl];
+  const uint32_t a = first_true_u32(0u, n, [&](uint32_t j) { return s.tm[tile_at(t, Cl, (int)j)] >= lo; });
+  const uint32_t b = first_true_u32(a, n, [&](uint32_t j) { return s.tm[tile_at(t, Cl, (int)j)] > hi; });
+  return range_mask(a, b);
+}
+
+// Exact pruning of the 4-hit candidates of one passing anchor pair.
+//
+// For fixed inputs r_l (x of the hit at the track's y minus the straight line), w_l and a_l, the
+// fit's chi2 is the minimum over q of sum_l w_l (r_l - a_l q)^2 (Sections III-C, V-B).  Adding a hit
+// adds a non-negative term, so the chi2 of (A, B, c1, c2) is at least that of (A, B, c1), which in
+// closed form is chi2_AB + S w (r - a q_AB)^2 / (S + w a^2) with S = k_A + k_B, k = w a^2, and q_AB,
+// chi2_AB the two-anchor fit.  A candidate can only be selected if its binary32 chi2 is <= U, the
+// binary32 chi2 of a 4-hit candidate of the track already evaluated.  The binary32 evaluation
+// undershoots the real minimum by at most
+//   E <= 7u chi2 + 2.02u sqrt(chi2) |q| sqrt(Saa),   u = 2^-24,
+// (roundings of the products and sums, and of r - a*q at the computed q; |q| <= max |r/a| of the
+// hits, Saa <= S + the largest k of each completion layer).  So a completion hit whose bound
+// exceeds U + 4E (+ a relative 1e-6) cannot be in the selected candidate, whatever the other hit
+// is.  The bound is evaluated in binary64 from the binary32 inputs.  Pruning changes which
+// candidates are evaluated, never the result; it is skipped where its premises fail.
+struct PairFit {
+  double S, qab, chi2ab, Z;     // anchor curvature, two-anchor q and chi2, max|q| * sqrt(max Saa)
+  float lb;                     // chi2_AB + the larger of the per-layer nearest-hit scores
+  uint32_t seed1, seed2;        // window slots of the nearest completion hits
+};
+
+__device__ inline void pair_fit(const Geom& g, const GroupScratch& s, int t, int A, int B, int C1,
+                                int C2, int jA, int jB, uint32_t m1, uint32_t m2, PairFit& f) {
+  const int oA = tile_at(t, A, jA), oB = tile_at(t, B, jB);
+  const float rA = s.tm[oA] - s.xs[t * 4 + A], rB = s.tm[oB] - s.xs[t * 4 + B];
+  const double wA = s.tw[oA], wB = s.tw[oB];
+  const double aA = g.a_kick[A], aB = g.a_kick[B];
+  const double kA = wA * aA * aA, kB = wB * aB * aB;
+  f.S = kA + kB;
+  f.qab = (wA * aA * (double)rA + wB * aB * (double)rB) / f.S;
+  const double eA = (double)rA - aA * f.qab, eB = (double)rB - aB * f.qab;
+  f.chi2ab = wA * eA * eA + wB * eB * eB;
+  double rmax = fmax(fabs((double)rA) / aA, fabs((double)rB) / aB);
+  double kmax[2], smin[2];
+  uint32_t arg[2];
+  const int Cs[2] = {C1, C2};
+  const uint32_t ms[2] = {m1, m2};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int Cl = Cs[k];
+    const double a = g.a_kick[Cl];
+    const float xsl = s.xs[t * 4 + Cl];
+    kmax[k] = 0.0;
+    smin[k] = 0.0;
+    arg[k] = 0;
+    bool any = false;
+    for (uint32_t m = ms[k]; m; m &= m - 1) {
+      const uint32_t j = (uint32_t)__builtin_ctz(m);
+      const int o = tile_at(t, Cl, (int)j);
+      const float r = s.tm[o] - xsl;
+      const double w = s.tw[o];
+      const double e = (double)r - a * f.qab;
+      const double score = w * e * e;   // steers the seed only; any choice is correct
+      if (!any || score < smin[k]) { smin[k] = score; arg[k] = j; any = true; }
+      kmax[k] = fmax(kmax[k], w * a * a);
+      rmax = fmax(rmax, fabs((double)r) / a);
+    }
   }
-  return mk;
+  f.Z = rmax * sqrt(f.S + kmax[0] + kmax[1]);
+  f.lb = (float)(f.chi2ab + fmax(smin[0], smin[1]));
+  f.seed1 = arg[0];
+  f.seed2 = arg[1];
+}
+
+// Completion hits of layer Cl (mask m) that can still be in a selected candidate, given U.
+__device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
+                                      const PairFit& f, double U) {
+  constexpr double u = 5.9604644775390625e-08;   // 2^-24
+  const double E = 7.0 * u * (2.0 * U + 1.0) + 2.02 * u * sqrt(2.0 * U + 1.0) * f.Z;
+  if (!(E <= U + 1.0) || !isfinite(f.chi2ab)) return m;   // premises fail: keep all
+  const double room = (U + 4.0 * E + 1e-6 * (U + 1.0)) - f.chi2ab;
+  if (room < 0.0) return 0u;
+  const double a = g.a_kick[Cl];
+  const float xsl = s.xs[t * 4 + Cl];
+  uint32_t keep = 0;
+  for (uint32_t mm = m; mm; mm &= mm - 1) {
+    const uint32_t j = (uint32_t)__builtin_ctz(mm);
+    const int o = tile_at(t, Cl, (int)j);
+    const float r = s.tm[o] - xsl;
+    const double w = s.tw[o];
+    const double e = (double)r - a * f.qab;
+    if (f.S * w * e * e <= room * (f.S + w * a * a) * (1.0 + 1e-12)) keep |= 1u << j;
+  }
+  return keep;
+}
+
+// One batch of at most 64 passing anchor pairs (s.bp, pairs of one track contiguous): completion
+// masks, for 4-hit candidates the seed and the pruning, then the candidates flattened over the
+// lanes; each candidate's key is folded into its track's minimum.
+__device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratch& s, int A, int B,
+                                 int C1, int C2, float inv_dz_ab, int nhits, uint32_t np) {
+  const int lane = lane_id();
+  uint32_t m1 = 0, m2 = 0;
+  int tt = 0, jA = 0, jB = 0;
+  if ((uint32_t)lane < np) {
+    const uint32_t b = s.bp[lane];
+    tt = (int)(b & 0xFFu);
+    jA = (int)((b >> 8) & 0xFFu);
+    jB = (int)(b >> 16);
+    const float mA = s.tm[tile_at(tt, A, jA)];
+    const float mB = s.tm[tile_at(tt, B, jB)];
+    const float slope = (mB - mA) * inv_dz_ab;
+    m1 = completion_range(g, p, s, tt, A, C1, mA, slope) & s.umask[tt * 4 + C1];
+    m2 = completion_range(g, p, s, tt, A, C2, mA, slope) & s.umask[tt * 4 + C2];
+  }
+  if (nhits == 4 && p.prune) {
+    // one seed per track and batch: the candidate of the pair with the lowest two-anchor bound,
+    // with the completion hits nearest to the two-anchor fit; its chi2 bounds the rest
+    const bool multi = (uint32_t)lane < np && m1 && m2 && __popc(m1) * __popc(m2) > 1;
+    PairFit pf;
+    if (lane < kGroupTracks) s.lbk[lane] = kNoKey;
+    wave_sync();
+    if (multi) {
+      pair_fit(g, s, tt, A, B, C1, C2, jA, jB, m1, m2, pf);
+      atomicMin(&s.lbk[tt], ((unsigned long long)__float_as_uint(pf.lb) << 32) | (unsigned)lane);
+    }
+    wave_sync();
+    if (multi && (uint32_t)(s.lbk[tt] & 0xFFFFFFFFull) == (uint32_t)lane) {
+      uint32_t code[4];
+      code[A] = (uint32_t)jA + 1u;
+      code[B] = (uint32_t)jB + 1u;
+      code[C1] = pf.seed1 + 1u;
+      code[C2] = pf.seed2 + 1u;
+      float qs, cs;
+      fit_codes(g, s, tt, code, qs, cs);
+      atomicMin(&s.best[tt], make_key(4, cs, code));
+    }
+    wave_sync();
+    if (multi) {
+      const unsigned long long bk = s.best[tt];
+      const double U = (double)__uint_as_float((uint32_t)(bk >> 24));
+      if (bk != kNoKey && isfinite(U)) {
+        m1 = prune_mask(g, s, tt, C1, m1, pf, U);
+        m2 = prune_mask(g, s, tt, C2, m2, pf, U);
+      }
+    }
+  }
+  uint32_t ncand = 0;
+  if ((uint32_t)lane < np) {
+    s.bm1[lane] = m1;
+    s.bm2[lane] = m2;
+    const uint32_t n1 = (uint32_t)__popc(m1), n2 = (uint32_t)__popc(m2);
+    ncand = nhits == 4 ? n1 * n2 : n1 + n2;
+  }
+  uint32_t ctot;
+  const uint32_t coff = wave_excl_scan(ncand, &ctot);
+  s.boff[lane] = coff;
+  if (lane == 0) s.boff[kWave] = ctot;
+  wave_sync();
+  // candidates of the batch, one per lane
+  for (uint32_t cb = 0; cb < ctot; cb += kWave) {
+    const uint32_t ci = cb + (uint32_t)lane;
+    if (ci < ctot) {
+      const uint32_t pi = first_true_u32(0u, np, [&](uint32_t k) { return s.boff[k + 1] > ci; });
+      const uint32_t rr = ci - s.boff[pi];
+      const uint32_t c1m = s.bm1[pi], c2m = s.bm2[pi];
+      uint32_t k1, k2;  // window slot + 1 of the completion hits, 0 = none
+      if (nhits == 4) {
+        const uint32_t n2 = (uint32_t)__popc(c2m);
+        const uint32_t i1 = rr / n2;
+        k1 = nth_set_bit(c1m, i1) + 1u;
+        k2 = nth_set_bit(c2m, rr - i1 * n2) + 1u;
+      } else {
+        const uint32_t n1 = (uint32_t)__popc(c1m);
+        k1 = rr < n1 ? nth_set_bit(c1m, rr) + 1u : 0u;
+        k2 = rr < n1 ? 0u : nth_set_bit(c2m, rr - n1) + 1u;
+      }
+      const uint32_t b = s.bp[pi];
+      const int t2 = (int)(b & 0xFFu);
+      const uint32_t a1 = (b >> 8) & 0xFFu, b1 = b >> 16;
+      uint32_t code[4];
+#pragma unroll
+      for (int q = 0; q < kLayers; ++q)
+        code[q] = q == A ? a1 + 1u : q == B ? b1 + 1u : q == C1 ? k1 : k2;
+      float qop, chi2;
+      fit_codes(g, s, t2, code, qop, chi2);
+      atomicMin(&s.best[t2], make_key(nhits, chi2, code));
+    }
+  }
+  wave_sync();
 }
 
 // The candidates of one direction with `nhits` hits (4: both completion layers; 3: one of them) for
-// the tracks with want_lane set (read on their layer-0 lane).  Anchor pairs are flattened over the
-// lanes; the pairs that pass the slope test are compacted into a batch, their completion masks
-// computed, and the batch's candidates flattened over the lanes again, so that every lane fits a
-// real candidate.  Each candidate's key is folded into its track's minimum.
+// the tracks with want_lane set (read on their layer-0 lane).  Work items are (track, anchor-A
+// hit); each finds its passing anchor-B hits as one slot range, and the passing pairs are handed
+// out in batches of at most 64.
 __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupScratch& s, int dir,
                                      int nhits, bool want_lane) {
   const int lane = lane_id();
   const int t = lane >> 2, l = lane & 3;
   int A, B, C1, C2;
   dir_layers(dir, A, B, C1, C2);
-  const uint32_t cnt = (l == 0 && want_lane) ? (uint32_t)(s.nwin[t * 4 + A] * s.nwin[t * 4 + B]) : 0u;
+  const float inv_dz_ab = 1.0f / (g.z_layer[B] - g.z_layer[A]);
+  const uint32_t cnt = (l == 0 && want_lane) ? (uint32_t)s.nwin[t * 4 + A] : 0u;
   uint32_t total;
   const uint32_t off = wave_excl_scan(cnt, &total);
   if (l == 0) s.poff[t] = off;
   if (lane == 0) s.poff[kGroupTracks] = total;
   wave_sync();
   for (uint32_t base = 0; base < total; base += kWave) {
-    // slope test of one pair per lane
     const uint32_t it = base + (uint32_t)lane;
-    bool pass = false;
-    uint32_t info = 0;
+    uint32_t rem = 0;    // anchor-B slots still to be paired with this lane's anchor-A hit
+    uint32_t head = 0;   // track | anchor-A slot << 8
     if (it < total) {
       const int tt = (int)first_true_u32(0u, (uint32_t)kGroupTracks,
                                          [&](uint32_t k) { return s.poff[k + 1] > it; });
-      const uint32_t r = it - s.poff[tt];
-      const uint32_t nb = (uint32_t)s.nwin[tt * 4 + B];
-      const uint32_t jA = r / nb, jB = r - jA * nb;
-      float mA, slope;
-      pass = pair_slope(g, p, s, tt, A, B, (int)jA, (int)jB, mA, slope);
-      info = (uint32_t)tt | (jA << 8) | (jB << 16);
-    }
-    const uint64_t pm = ballot(pass);
-    const uint32_t np = (uint32_t)__popcll(pm);
-    if (np == 0) continue;
-    if (pass) s.bp[lanes_before(pm)] = info;
-    wave_sync();
-    // completion masks of the batch, one pair per lane
-    uint32_t ncand = 0;
-    if ((uint32_t)lane < np) {
-      const uint32_t b = s.bp[lane];
-      const int tt = (int)(b & 0xFFu);
-      const int jA = (int)((b >> 8) & 0xFFu), jB = (int)(b >> 16);
-      float mA, slope;
-      pair_slope(g, p, s, tt, A, B, jA, jB, mA, slope);
-      const uint32_t m1 = completion_mask(g, p, s, tt, A, C1, mA, slope);
-      const uint32_t m2 = completion_mask(g, p, s, tt, A, C2, mA, slope);
-      s.bm1[lane] = m1;
-      s.bm2[lane] = m2;
-      const uint32_t n1 = (uint32_t)__popc(m1), n2 = (uint32_t)__popc(m2);
-      ncand = nhits == 4 ? n1 * n2 : n1 + n2;
-    }
-    uint32_t ctot;
-    const uint32_t coff = wave_excl_scan(ncand, &ctot);
-    s.boff[lane] = coff;
-    if (lane == 0) s.boff[kWave] = ctot;
-    wave_sync();
-    // candidates of the batch, one per lane
-    for (uint32_t cb = 0; cb < ctot; cb += kWave) {
-      const uint32_t ci = cb + (uint32_t)lane;
-      if (ci < ctot) {
-        const uint32_t pi = first_true_u32(0u, np, [&](uint32_t k) { return s.boff[k + 1] > ci; });
-        const uint32_t rr = ci - s.boff[pi];
-        const uint32_t m1 = s.bm1[pi], m2 = s.bm2[pi];
-        uint32_t k1, k2;  // window slot + 1 of the completion hits, 0 = none
-        if (nhits == 4) {
-          const uint32_t n2 = (uint32_t)__popc(m2);
-          const uint32_t i1 = rr / n2;
-          k1 = nth_set_bit(m1, i1) + 1u;
-          k2 = nth_set_bit(m2, rr - i1 * n2) + 1u;
-        } else {
-          const uint32_t n1 = (uint32_t)__popc(m1);
-          k1 = rr < n1 ? nth_set_bit(m1, rr) + 1u : 0u;
-          k2 = rr < n1 ? 0u : nth_set_bit(m2, rr - n1) + 1u;
-        }
-        const uint32_t b = s.bp[pi];
-        const int tt = (int)(b & 0xFFu);
-        const uint32_t jA = (b >> 8) & 0xFFu, jB = b >> 16;
-        uint32_t code[4];
-#pragma unroll
-        for (int q = 0; q < kLayers; ++q)
-          code[q] = q == A ? jA + 1u : q == B ? jB + 1u : q == C1 ? k1 : k2;
-        float qop, chi2;
-        fit_codes(g, s, tt, code, qop, chi2);
-        atomicMin(&s.best[tt], make_key(nhits, chi2, code));
+      const uint32_t jA = it - s.poff[tt];
+      head = (uint32_t)tt | (jA << 8);
+      if ((s.umask[tt * 4 + A] >> jA) & 1u) {
+        const float mA = s.tm[tile_at(tt, A, (int)jA)];
+        rem = slope_range(s, tt, B, mA, inv_dz_ab, s.tx[tt], p.slope_tol) & s.umask[tt * 4 + B];
       }
     }
-    wave_sync();
+    while (wave_any(rem != 0u)) {
+      const uint32_t c = (uint32_t)__popc(rem);
+      uint32_t tot;
+      const uint32_t o = wave_excl_scan(c, &tot);
+      // slots left in the batch for this lane, written without a branch: a conditional form
+      // (o >= 64 ? 0 : 64 - o) has been folded by the compiler into the wrapping 64 - o
+      const uint32_t room = (uint32_t)kWave - min(o, (uint32_t)kWave);
+      const uint32_t take = min(c, room);
+      for (uint32_t k = 0; k < take; ++k) {
+        const uint32_t jB = (uint32_t)__builtin_ctz(rem);
+        rem &= rem - 1u;
+        s.bp[o + k] = head | (jB << 16);
+      }
+      wave_sync();
+      run_batch(g, p, s, A, B, C1, C2, inv_dz_ab, nhits, min(tot, (uint32_t)kWave));
+    }
   }
   wave_sync();
 }
@@ -354,6 +514,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   }
   // tile: x at the track's y and weight of each window hit; -1 marks a strip that does not cover y
   const float g_yb = g.y_begin, g_ye = g.y_end;
+  uint32_t umask = 0;
   for (int j0 = 0; j0 < wn; j0 += 4) {
     float uu[4], ww[4], yb[4], ye[4];
 #pragma unroll
@@ -376,11 +537,14 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (j0 + q < wn) {
+        const float w = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
         s.tm[tile_at(t, l, j0 + q)] = uu[q] + yl * g.dxdy[l];
-        s.tw[tile_at(t, l, j0 + q)] = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
+        s.tw[tile_at(t, l, j0 + q)] = w;
+        if (w >= 0.0f) umask |= 1u << (j0 + q);
       }
     }
   }
+  s.umask[lane] = umask;
   wave_sync();
 
   // tracklets (Section V-B): forward anchors first; backward only where forward found nothing
