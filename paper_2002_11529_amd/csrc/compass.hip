@@ -137,12 +137,10 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   p.half = (params->n_sectors_search - 1) / 2;
   p.slope_tol = params->slope_tol;
   p.eps = params->completion_tol;
-  // the pruning bound needs positive kick factors and non-negative finite weights
+  // the pruning bound needs positive kick factors
   p.prune = 1;
   for (int l = 0; l < kLayers; ++l)
     if (!(geom->a_kick[l] > 0.0f) || !std::isfinite(geom->a_kick[l])) p.prune = 0;
-  for (int i = 0; i < 16; ++i)
-    if (!(geom->weight_by_size[i] >= 0.0f) || !std::isfinite(geom->weight_by_size[i])) p.prune = 0;
   const int block = launch ? launch->block : 256;
   const int waves = block / kWave;
   // stage u of events up to u_cap hits, keeping the workgroup's LDS at or under 40 KiB so that

@@ -23,7 +23,7 @@ struct CPar {
   int half;           // (n_sectors_search - 1) / 2
   float slope_tol;
   float eps;          // completion interval margin (mm)
-  int prune;          // lower-bound pruning of 4-hit candidates allowed (kick factors > 0, weights >= 0)
+  int prune;          // lower-bound pruning of 4-hit candidates allowed (kick factors > 0)
 };
 
 // Hits of the current event as seen by the search.  kULds / kWLds: u / weight read from LDS
@@ -65,6 +65,7 @@ struct GroupScratch {
   unsigned long long* best;  // [16] selection key minimum
   unsigned long long* lbk;   // [16] seed choice of the batch: two-anchor bound << 32 | lane
   uint32_t* umask;    // [64] usable window slots (strip covers the track's y)
+  float* wmax;        // [64] largest weight of the usable slots
   uint32_t* poff;     // [17] pair offsets of the tracks
   uint32_t* bp;       // [64] batch of anchor pairs that passed the slope test: t | jA<<8 | jB<<16
   uint32_t* bm1;      // [64] their completion masks in layer C1
@@ -73,7 +74,7 @@ struct GroupScratch {
 };
 
 __host__ __device__ inline size_t group_scratch_bytes(int max_hits) {
-  const size_t b = 16 * kGroupTracks + 4 * 64 + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
+  const size_t b = 16 * kGroupTracks + 8 * 64 + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
                    4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65;
   return (b + 15) / 16 * 16;
 }
@@ -83,7 +84,8 @@ __device__ inline GroupScratch carve_group(char* p, int max_hits) {
   s.best = reinterpret_cast<unsigned long long*>(p);
   s.lbk = s.best + kGroupTracks;
   s.umask = reinterpret_cast<uint32_t*>(s.lbk + kGroupTracks);
-  s.tm = reinterpret_cast<float*>(s.umask + 64);
+  s.wmax = reinterpret_cast<float*>(s.umask + 64);
+  s.tm = s.wmax + 64;
   s.tw = s.tm + 64 * max_hits;
   s.xs = s.tw + 64 * max_hits;
   s.tx = s.xs + 64;
@@ -177,15 +179,22 @@ __device__ inline uint32_t slope_range(const GroupScratch& s, int t, int B, floa
   return range_mask(lo, hi);
 }
 
+// Completion interval of layer Cl for a pair (the one completion_range searches).
+__device__ inline void completion_bounds(const Geom& g, const CPar& p, const GroupScratch& s, int t,
+                                         int A, int Cl, float mA, float slope, float& lo, float& hi) {
+  const float d = g.z_layer[Cl] - g.z_layer[A];
+  const float xt = mA + slope * d;
+  const float xv = mA + s.tx[t] * d;
+  lo = fminf(xt, xv) - p.eps;
+  hi = fmaxf(xt, xv) + p.eps;
+}
+
 // Completion slots of a passing pair in layer Cl: x inside the interval spanned by the pair-slope
 // and VELO-slope extrapolations from the first anchor, widened by the completion tolerance.
 __device__ inline uint32_t completion_range(const Geom& g, const CPar& p, const GroupScratch& s,
                                             int t, int A, int Cl, float mA, float slope) {
-  const float d = g.z_layer[Cl] - g.z_layer[A];
-  const float xt = mA + slope * d;
-  const float xv = mA + s.tx[t] * d;
-  const float lo = fminf(xt, xv) - p.eps;
-  const float hi = fmaxf(xt, xv) + p.eps;
+  float lo, hi;
+  completion_bounds(g, p, s, t, A, Cl, mA, slope, lo, hi);
   const uint32_t n = (uint32_t)s.nwin[t * 4 + Cl];
   const uint32_t a = first_true_u32(0u, n, [&](uint32_t j) { return s.tm[tile_at(t, Cl, (int)j)] >= lo; });
   const uint32_t b = first_true_u32(a, n, [&](uint32_t j) { return s.tm[tile_at(t, Cl, (int)j)] > hi; });
@@ -198,69 +207,63 @@ __device__ inline uint32_t completion_range(const Geom& g, const CPar& p, const 
 // fit's chi2 is the minimum over q of sum_l w_l (r_l - a_l q)^2 (Sections III-C, V-B).  Adding a hit
 // adds a non-negative term, so the chi2 of (A, B, c1, c2) is at least that of (A, B, c1), which in
 // closed form is chi2_AB + S w (r - a q_AB)^2 / (S + w a^2) with S = k_A + k_B, k = w a^2, and q_AB,
-// chi2_AB the two-anchor fit.  A candidate can only be selected if its binary32 chi2 is <= U, the
-// binary32 chi2 of a 4-hit candidate of the track already evaluated.  The binary32 evaluation
-// undershoots the real minimum by at most
+// chi2_AB the two-anchor fit; in particular it is at least chi2_AB.  A candidate can only be
+// selected if its binary32 chi2 is <= U, the binary32 chi2 of a 4-hit candidate of the track
+// already evaluated.  The binary32 evaluation undershoots the real minimum by at most
 //   E <= 7u chi2 + 2.02u sqrt(chi2) |q| sqrt(Saa),   u = 2^-24,
-// (roundings of the products and sums, and of r - a*q at the computed q; |q| <= max |r/a| of the
-// hits, Saa <= S + the largest k of each completion layer).  So a completion hit whose bound
-// exceeds U + 4E (+ a relative 1e-6) cannot be in the selected candidate, whatever the other hit
-// is.  The bound is evaluated in binary64 from the binary32 inputs.  Pruning changes which
-// candidates are evaluated, never the result; it is skipped where its premises fail.
-struct PairFit {
-  double S, qab, chi2ab, Z;     // anchor curvature, two-anchor q and chi2, max|q| * sqrt(max Saa)
-  float lb;                     // chi2_AB + the larger of the per-layer nearest-hit scores
-  uint32_t seed1, seed2;        // window slots of the nearest completion hits
+// (roundings of the products and sums, and of r - a*q at the computed q), with |q| <= max |r/a| over
+// the candidate's hits and Saa <= S + the largest k of each completion layer.  Both are bounded per
+// pair from the completion intervals (|r| of a completion hit is at most the larger distance of the
+// interval ends from the straight line) and the largest weight of the layer's window.  So a completion hit whose bound
+// exceeds U + 4E (+ a relative 1e-6) cannot be in the selected candidate, whatever the other hit is,
+// and a pair whose chi2_AB alone exceeds it has no such hit.  Bounds are evaluated in binary64 from
+// the binary32 inputs.  Pruning changes which candidates are evaluated, never the result; it is
+// skipped where its premises fail (non-finite values).
+struct AnchorFit {
+  double S, qab, chi2ab;
 };
 
-__device__ inline void pair_fit(const Geom& g, const GroupScratch& s, int t, int A, int B, int C1,
-                                int C2, int jA, int jB, uint32_t m1, uint32_t m2, PairFit& f) {
+__device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int t, int A, int B,
+                                       int jA, int jB) {
   const int oA = tile_at(t, A, jA), oB = tile_at(t, B, jB);
-  const float rA = s.tm[oA] - s.xs[t * 4 + A], rB = s.tm[oB] - s.xs[t * 4 + B];
+  const double rA = s.tm[oA] - s.xs[t * 4 + A], rB = s.tm[oB] - s.xs[t * 4 + B];
   const double wA = s.tw[oA], wB = s.tw[oB];
   const double aA = g.a_kick[A], aB = g.a_kick[B];
-  const double kA = wA * aA * aA, kB = wB * aB * aB;
-  f.S = kA + kB;
-  f.qab = (wA * aA * (double)rA + wB * aB * (double)rB) / f.S;
-  const double eA = (double)rA - aA * f.qab, eB = (double)rB - aB * f.qab;
+  AnchorFit f;
+  f.S = wA * aA * aA + wB * aB * aB;
+  f.qab = (wA * aA * rA + wB * aB * rB) / f.S;
+  const double eA = rA - aA * f.qab, eB = rB - aB * f.qab;
   f.chi2ab = wA * eA * eA + wB * eB * eB;
-  double rmax = fmax(fabs((double)rA) / aA, fabs((double)rB) / aB);
-  double kmax[2], smin[2];
-  uint32_t arg[2];
+  return f;
+}
+
+// Upper bound of |q| * sqrt(Saa) over the 4-hit candidates of a pair.
+__device__ inline double pair_z(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
+                                int B, int C1, int C2, int jA, int jB, float mA, float slope,
+                                const AnchorFit& f) {
+  const double rA = s.tm[tile_at(t, A, jA)] - s.xs[t * 4 + A];
+  const double rB = s.tm[tile_at(t, B, jB)] - s.xs[t * 4 + B];
+  double rmax = fmax(fabs(rA) / (double)g.a_kick[A], fabs(rB) / (double)g.a_kick[B]);
+  double kC = 0.0;
   const int Cs[2] = {C1, C2};
-  const uint32_t ms[2] = {m1, m2};
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int Cl = Cs[k];
-    const double a = g.a_kick[Cl];
-    const float xsl = s.xs[t * 4 + Cl];
-    kmax[k] = 0.0;
-    smin[k] = 0.0;
-    arg[k] = 0;
-    bool any = false;
-    for (uint32_t m = ms[k]; m; m &= m - 1) {
-      const uint32_t j = (uint32_t)__builtin_ctz(m);
-      const int o = tile_at(t, Cl, (int)j);
-      const float r = s.tm[o] - xsl;
-      const double w = s.tw[o];
-      const double e = (double)r - a * f.qab;
-      const double score = w * e * e;   // steers the seed only; any choice is correct
-      if (!any || score < smin[k]) { smin[k] = score; arg[k] = j; any = true; }
-      kmax[k] = fmax(kmax[k], w * a * a);
-      rmax = fmax(rmax, fabs((double)r) / a);
-    }
+    float lo, hi;
+    completion_bounds(g, p, s, t, A, Cs[k], mA, slope, lo, hi);
+    const double xsl = s.xs[t * 4 + Cs[k]];
+    const double a = g.a_kick[Cs[k]];
+    const double r = fmax(fabs((double)lo - xsl), fabs((double)hi - xsl)) * (1.0 + 1e-6);
+    rmax = fmax(rmax, r / a);
+    kC += (double)s.wmax[t * 4 + Cs[k]] * a * a;
   }
-  f.Z = rmax * sqrt(f.S + kmax[0] + kmax[1]);
-  f.lb = (float)(f.chi2ab + fmax(smin[0], smin[1]));
-  f.seed1 = arg[0];
-  f.seed2 = arg[1];
+  return rmax * sqrt(f.S + kC);
 }
 
 // Completion hits of layer Cl (mask m) that can still be in a selected candidate, given U.
 __device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
-                                      const PairFit& f, double U) {
+                                      const AnchorFit& f, double Z, double U) {
   constexpr double u = 5.9604644775390625e-08;   // 2^-24
-  const double E = 7.0 * u * (2.0 * U + 1.0) + 2.02 * u * sqrt(2.0 * U + 1.0) * f.Z;
+  const double E = 7.0 * u * (2.0 * U + 1.0) + 2.02 * u * sqrt(2.0 * U + 1.0) * Z;
   if (!(E <= U + 1.0) || !isfinite(f.chi2ab)) return m;   // premises fail: keep all
   const double room = (U + 4.0 * E + 1e-6 * (U + 1.0)) - f.chi2ab;
   if (room < 0.0) return 0u;
@@ -276,6 +279,24 @@ __device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int 
     if (f.S * w * e * e <= room * (f.S + w * a * a) * (1.0 + 1e-12)) keep |= 1u << j;
   }
   return keep;
+}
+
+// Window slot of the hit of mask m in layer Cl nearest (weighted) to the two-anchor fit.
+__device__ inline uint32_t nearest_slot(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
+                                        double qab) {
+  const double a = g.a_kick[Cl];
+  const float xsl = s.xs[t * 4 + Cl];
+  double best = 0.0;
+  uint32_t arg = 0;
+  bool any = false;
+  for (uint32_t mm = m; mm; mm &= mm - 1) {
+    const uint32_t j = (uint32_t)__builtin_ctz(mm);
+    const int o = tile_at(t, Cl, (int)j);
+    const double e = (double)(s.tm[o] - xsl) - a * qab;
+    const double sc = (double)s.tw[o] * e * e;
+    if (!any || sc < best) { best = sc; arg = j; any = true; }
+  }
+  return arg;
 }
 
 // One batch of at most 64 passing anchor pairs (s.bp, pairs of one track contiguous): completion
@@ -298,23 +319,23 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     m2 = completion_range(g, p, s, tt, A, C2, mA, slope) & s.umask[tt * 4 + C2];
   }
   if (nhits == 4 && p.prune) {
-    // one seed per track and batch: the candidate of the pair with the lowest two-anchor bound,
-    // with the completion hits nearest to the two-anchor fit; its chi2 bounds the rest
+    // one seed per track and batch: the pair with the lowest two-anchor chi2, with the completion
+    // hits nearest to its fit; the seed's chi2 bounds the rest of the track's candidates
     const bool multi = (uint32_t)lane < np && m1 && m2 && __popc(m1) * __popc(m2) > 1;
-    PairFit pf;
+    AnchorFit af;
     if (lane < kGroupTracks) s.lbk[lane] = kNoKey;
     wave_sync();
     if (multi) {
-      pair_fit(g, s, tt, A, B, C1, C2, jA, jB, m1, m2, pf);
-      atomicMin(&s.lbk[tt], ((unsigned long long)__float_as_uint(pf.lb) << 32) | (unsigned)lane);
+      af = anchor_fit(g, s, tt, A, B, jA, jB);
+      atomicMin(&s.lbk[tt], ((unsigned long long)__float_as_uint((float)af.chi2ab) << 32) | (unsigned)lane);
     }
     wave_sync();
     if (multi && (uint32_t)(s.lbk[tt] & 0xFFFFFFFFull) == (uint32_t)lane) {
       uint32_t code[4];
       code[A] = (uint32_t)jA + 1u;
       code[B] = (uint32_t)jB + 1u;
-      code[C1] = pf.seed1 + 1u;
-      code[C2] = pf.seed2 + 1u;
+      code[C1] = nearest_slot(g, s, tt, C1, m1, af.qab) + 1u;
+      code[C2] = nearest_slot(g, s, tt, C2, m2, af.qab) + 1u;
       float qs, cs;
       fit_codes(g, s, tt, code, qs, cs);
       atomicMin(&s.best[tt], make_key(4, cs, code));
@@ -324,8 +345,13 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
       const unsigned long long bk = s.best[tt];
       const double U = (double)__uint_as_float((uint32_t)(bk >> 24));
       if (bk != kNoKey && isfinite(U)) {
-        m1 = prune_mask(g, s, tt, C1, m1, pf, U);
-        m2 = prune_mask(g, s, tt, C2, m2, pf, U);
+        const float mA = s.tm[tile_at(tt, A, jA)];
+        const float slope = (s.tm[tile_at(tt, B, jB)] - mA) * inv_dz_ab;
+        const double Z = pair_z(g, p, s, tt, A, B, C1, C2, jA, jB, mA, slope, af);
+        if (isfinite(Z)) {
+          m1 = prune_mask(g, s, tt, C1, m1, af, Z, U);
+          m2 = m1 ? prune_mask(g, s, tt, C2, m2, af, Z, U) : 0u;
+        }
       }
     }
   }
@@ -515,6 +541,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   // tile: x at the track's y and weight of each window hit; -1 marks a strip that does not cover y
   const float g_yb = g.y_begin, g_ye = g.y_end;
   uint32_t umask = 0;
+  float wm = 0.0f;
   for (int j0 = 0; j0 < wn; j0 += 4) {
     float uu[4], ww[4], yb[4], ye[4];
 #pragma unroll
@@ -540,11 +567,15 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
         const float w = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
         s.tm[tile_at(t, l, j0 + q)] = uu[q] + yl * g.dxdy[l];
         s.tw[tile_at(t, l, j0 + q)] = w;
-        if (w >= 0.0f) umask |= 1u << (j0 + q);
+        if (w >= 0.0f) {
+          umask |= 1u << (j0 + q);
+          wm = fmaxf(wm, w);
+        }
       }
     }
   }
   s.umask[lane] = umask;
+  s.wmax[lane] = wm;
   wave_sync();
 
   // tracklets (Section V-B): forward anchors first; backward only where forward found nothing
