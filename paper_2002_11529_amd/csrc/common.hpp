@@ -61,21 +61,32 @@ __device__ inline void raise_flag(uint32_t* flags, uint32_t bit) {
   if (flags) atomicOr(flags, bit);
 }
 
-// Inclusive scan across one wavefront.
+// Inclusive scans across one wavefront with all 64 lanes active, in DPP data movement (no LDS
+// round trips): shifts right by 1, 2, 4 and 8 lanes inside each row of 16 lanes (lanes without a
+// source keep the identity), then the last lane of row 0 is added into row 1 and of row 2 into row
+// 3, then lane 31 into rows 2 and 3.
+template <class Op>
+__device__ inline uint32_t dpp_inclusive_scan(uint32_t v, uint32_t identity, Op op) {
+  const int id = (int)identity;
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return v;
+}
+
 __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  return x;
+  return dpp_inclusive_scan(x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
+__device__ inline uint32_t wave_inclusive_max(uint32_t x) {
+  return dpp_inclusive_scan(x, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
 }
 
 __device__ inline uint32_t wave_sum(uint32_t x) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_inclusive_scan(x), 63);
 }
 
 // Exclusive scan across the workgroup.  `tmp` holds blockDim.x/64 + 1 words of LDS.  All threads
@@ -132,7 +143,7 @@ __device__ inline T wave_bcast(T v, int src) { return __shfl(v, src, kWave); }
 
 __device__ inline uint32_t wave_excl_scan(uint32_t x, uint32_t* total) {
   const uint32_t inc = wave_inclusive_scan(x);
-  *total = __shfl(inc, kWave - 1, kWave);
+  *total = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
   return inc - x;
 }
 

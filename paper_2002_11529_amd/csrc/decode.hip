@@ -75,6 +75,7 @@ k_decode(Geom g, const uint16_t* __restrict__ words, const uint32_t* __restrict_
   for (int u = blockIdx.x * nwaves + wid; u < n_units; u += gridDim.x * nwaves) {
     const int64_t b0 = (int64_t)u * g.S;
     const UnitCount st = unit_count(g, words, bank_offsets, b0, ws, flags);
+    stage_tables(g, u % kLayers, ws);
     unit_write(g, words, u % kLayers, b0, unit_base[u], st, ws, capacity, hit_offsets, out, flags,
                nullptr, nullptr, 0);
     wave_sync();

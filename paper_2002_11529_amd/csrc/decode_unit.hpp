@@ -26,11 +26,13 @@ struct WaveScratch {
   uint32_t* key;    // [kCap] valid words in bank order as (word << 16) | index: the sort key
   uint16_t* cbank;  // [kCap] bank of each valid word in bank order
   uint16_t* mark;   // [kCap] bank start markers by raw position, then valid words before it
+  float* u0;        // [S] bin-0 position of each sector of the unit's layer
+  float* wt;        // [16] weight of each cluster size
 };
 
 __host__ __device__ inline size_t wave_scratch_bytes(int S) {
   const size_t b = 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(uint32_t) * (size_t)kCap +
-                   3 * sizeof(uint16_t) * (size_t)kCap;
+                   3 * sizeof(uint16_t) * (size_t)kCap + sizeof(float) * ((size_t)S + 16);
   return (b + 15) / 16 * 16;
 }
 
@@ -42,6 +44,8 @@ __device__ inline WaveScratch carve_scratch(char* p, int S) {
   w.raw = reinterpret_cast<uint16_t*>(w.key + kCap);
   w.cbank = w.raw + kCap;
   w.mark = w.cbank + kCap;
+  w.u0 = reinterpret_cast<float*>(w.mark + kCap);
+  w.wt = w.u0 + S;
   return w;
 }
 
@@ -109,6 +113,14 @@ __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict
     st.T = wave_sum(c);
   }
   return st;
+}
+
+// The layer's sector positions and the weight table to LDS (lookups of every hit of the unit).
+__device__ inline void stage_tables(const Geom& g, int layer, const WaveScratch& ws) {
+  const int lane = lane_id();
+  for (int s = lane; s < g.S; s += kWave) ws.u0[s] = g.u0[layer * g.S + s];
+  if (lane < 16) ws.wt[lane] = g.weight_by_size[lane];
+  wave_sync();
 }
 
 // Decode one raw word of sector s in layer `layer`.
@@ -236,14 +248,9 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       const uint32_t i = i0 + lane;
       const uint16_t v = i < n ? ws.raw[i] : (uint16_t)0;
       const bool valid = (v & 0xFu) != 0u;
-      uint32_t bk = i < n ? (uint32_t)ws.mark[i] : 0u;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(bk, o, kWave);
-        if (lane >= o) bk = bk > y ? bk : y;
-      }
+      uint32_t bk = wave_inclusive_max(i < n ? (uint32_t)ws.mark[i] : 0u);
       bk = bk > bank_carry ? bk : bank_carry;
-      bank_carry = wave_bcast(bk, kWave - 1);
+      bank_carry = (uint32_t)__builtin_amdgcn_readlane((int)bk, kWave - 1);
       const uint64_t m = ballot(valid);
       const uint32_t pos = run + lanes_before(m);
       if (i < n) ws.mark[i] = (uint16_t)pos;
@@ -268,11 +275,23 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
     for (uint32_t k = lane; k < nh; k += kWave) {
       const int bk = ws.cbank[k];
       const uint32_t mine = ws.key[k];
+      const uint32_t v = mine >> 16;
+      // table lookups first, so that their latency overlaps the rank loop
+      const float u0 = ws.u0[bk];
+      const float w = ws.wt[v & 0xFu];
       const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
       uint32_t rank = 0;
-      for (uint32_t j = lo; j < hi; ++j) rank += ws.key[j] < mine;
+      uint32_t j = lo;
+      for (; j + 4 <= hi; j += 4)
+        rank += (uint32_t)(ws.key[j] < mine) + (uint32_t)(ws.key[j + 1] < mine) +
+                (uint32_t)(ws.key[j + 2] < mine) + (uint32_t)(ws.key[j + 3] < mine);
+      for (; j < hi; ++j) rank += ws.key[j] < mine;
       const uint32_t slot = lo + rank;
-      const DecodedHit d = decode_word(g, layer, (uint32_t)bk, mine >> 16);
+      const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
+      DecodedHit d;
+      d.lhcbid = ((uint32_t)layer << 28) | ((uint32_t)bk << 12) | (strip << 3) | frac;
+      d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0);
+      d.w = w;
       store_hit(g, layer, d, (int64_t)base + local + slot, capacity, out, flags);
       if (lds_u) {
         lds_u[lds_first + local + slot] = d.u;
