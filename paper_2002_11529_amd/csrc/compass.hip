@@ -78,12 +78,20 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     ev.overflow = overflow;
     const uint32_t t0 = velo_offsets[e], t1 = velo_offsets[e + 1];
     const uint32_t ngroups = (t1 - t0 + kGroupTracks - 1) / kGroupTracks;
+    // the next group's VELO states are loaded while the current group is searched
+    LaneState st = load_state(io, t0 + wid * kGroupTracks, t1);
     if (staged) {
-      for (uint32_t grp = wid; grp < ngroups; grp += nwaves)
-        compass_group<true, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io);
+      for (uint32_t grp = wid; grp < ngroups; grp += nwaves) {
+        const LaneState next = load_state(io, t0 + (grp + nwaves) * kGroupTracks, t1);
+        compass_group<true, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
+        st = next;
+      }
     } else {
-      for (uint32_t grp = wid; grp < ngroups; grp += nwaves)
-        compass_group<false, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io);
+      for (uint32_t grp = wid; grp < ngroups; grp += nwaves) {
+        const LaneState next = load_state(io, t0 + (grp + nwaves) * kGroupTracks, t1);
+        compass_group<false, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
+        st = next;
+      }
     }
     __syncthreads();
   }
@@ -143,10 +151,17 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
     if (!(geom->a_kick[l] > 0.0f) || !std::isfinite(geom->a_kick[l])) p.prune = 0;
   const int block = launch ? launch->block : 256;
   const int waves = block / kWave;
-  // stage u of events up to u_cap hits, keeping the workgroup's LDS at or under 40 KiB so that
-  // four workgroups share a CU; larger events search global memory
+  // stage u of events up to u_cap hits, keeping the workgroup's LDS within its share of the CU's
+  // 160 KiB at the occupancy the kernel's registers allow; larger events search global memory
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compass, block, 0) != hipSuccess || per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  const size_t budget = (size_t)160 * 1024 / (size_t)per_cu;
   const size_t fixed = compass_lds_bytes(g.S, p.max_hits, waves, 0);
-  int u_cap = fixed < 40 * 1024 ? (int)((40 * 1024 - fixed) / sizeof(float)) / 64 * 64 : 0;
+  int u_cap = fixed < budget ? (int)((budget - fixed) / sizeof(float)) / 64 * 64 : 0;
+  if (u_cap > 1 << 20) u_cap = 1 << 20;
   const size_t lds = compass_lds_bytes(g.S, p.max_hits, waves, u_cap);
   if (lds > 160 * 1024) return UTC_ERR_ARG;
   (void)hipGetLastError();  // report only errors of this call

@@ -16,6 +16,7 @@
 namespace utc {
 
 constexpr int kGroupTracks = 16;
+constexpr int kPruneMinCandidates = 256;   // 4-hit candidates of a batch below which no pruning
 
 struct CPar {
   float W;            // window half-width (mm)
@@ -206,21 +207,26 @@ __device__ inline uint32_t completion_range(const Geom& g, const CPar& p, const 
 // For fixed inputs r_l (x of the hit at the track's y minus the straight line), w_l and a_l, the
 // fit's chi2 is the minimum over q of sum_l w_l (r_l - a_l q)^2 (Sections III-C, V-B).  Adding a hit
 // adds a non-negative term, so the chi2 of (A, B, c1, c2) is at least that of (A, B, c1), which in
-// closed form is chi2_AB + S w (r - a q_AB)^2 / (S + w a^2) with S = k_A + k_B, k = w a^2, and q_AB,
-// chi2_AB the two-anchor fit; in particular it is at least chi2_AB.  A candidate can only be
-// selected if its binary32 chi2 is <= U, the binary32 chi2 of a 4-hit candidate of the track
-// already evaluated.  The binary32 evaluation undershoots the real minimum by at most
+// closed form is chi2_AB + S w e^2 / (S + w a^2), e = r - a q_AB, with S = k_A + k_B, k = w a^2, and
+// q_AB = N / S, N = sum w a r, chi2_AB the two-anchor fit; in particular it is at least chi2_AB.  A
+// candidate can only be selected if its binary32 chi2 is <= U, the binary32 chi2 of a 4-hit
+// candidate of the track already evaluated.  The binary32 evaluation undershoots the real minimum
+// by at most
 //   E <= 7u chi2 + 2.02u sqrt(chi2) |q| sqrt(Saa),   u = 2^-24,
 // (roundings of the products and sums, and of r - a*q at the computed q), with |q| <= max |r/a| over
 // the candidate's hits and Saa <= S + the largest k of each completion layer.  Both are bounded per
 // pair from the completion intervals (|r| of a completion hit is at most the larger distance of the
-// interval ends from the straight line) and the largest weight of the layer's window.  So a completion hit whose bound
-// exceeds U + 4E (+ a relative 1e-6) cannot be in the selected candidate, whatever the other hit is,
-// and a pair whose chi2_AB alone exceeds it has no such hit.  Bounds are evaluated in binary64 from
-// the binary32 inputs.  Pruning changes which candidates are evaluated, never the result; it is
-// skipped where its premises fail (non-finite values).
+// interval ends from the straight line) and the largest weight of the layer's window.  So a
+// completion hit whose bound exceeds T = U + 4E (+ a relative 1e-6) cannot be in the selected
+// candidate, whatever the other hit is, and a pair whose chi2_AB alone exceeds T has no such hit.
+// The test is evaluated in binary64 from the binary32 inputs, multiplied through by S^2 (S + k) so
+// that it needs no division:  C (S + k) + S w (r S - a N)^2 <= T S^2 (S + k),  C = chi2_AB S^2.
+// E only enters as a margin and is bounded from above in binary32.  Pruning changes which
+// candidates are evaluated, never the result; it is skipped where its premises fail (non-finite
+// values).
 struct AnchorFit {
-  double S, qab, chi2ab;
+  double S, N, C;    // k_A + k_B, sum w a r, chi2_AB * S^2
+  float qab;         // approximate N / S (seed choice only)
 };
 
 __device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int t, int A, int B,
@@ -231,69 +237,73 @@ __device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int
   const double aA = g.a_kick[A], aB = g.a_kick[B];
   AnchorFit f;
   f.S = wA * aA * aA + wB * aB * aB;
-  f.qab = (wA * aA * rA + wB * aB * rB) / f.S;
-  const double eA = rA - aA * f.qab, eB = rB - aB * f.qab;
-  f.chi2ab = wA * eA * eA + wB * eB * eB;
+  f.N = wA * aA * rA + wB * aB * rB;
+  const double eA = rA * f.S - aA * f.N, eB = rB * f.S - aB * f.N;
+  f.C = wA * eA * eA + wB * eB * eB;
+  f.qab = __fdividef((float)f.N, (float)f.S);
   return f;
 }
 
-// Upper bound of |q| * sqrt(Saa) over the 4-hit candidates of a pair.
-__device__ inline double pair_z(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
-                                int B, int C1, int C2, int jA, int jB, float mA, float slope,
-                                const AnchorFit& f) {
-  const double rA = s.tm[tile_at(t, A, jA)] - s.xs[t * 4 + A];
-  const double rB = s.tm[tile_at(t, B, jB)] - s.xs[t * 4 + B];
-  double rmax = fmax(fabs(rA) / (double)g.a_kick[A], fabs(rB) / (double)g.a_kick[B]);
-  double kC = 0.0;
+// Upper bound of |q| * sqrt(Saa) over the 4-hit candidates of a pair, in binary32 rounded up.
+__device__ inline float pair_z(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
+                               int B, int C1, int C2, int jA, int jB, float mA, float slope,
+                               const AnchorFit& f) {
+  const float rA = s.tm[tile_at(t, A, jA)] - s.xs[t * 4 + A];
+  const float rB = s.tm[tile_at(t, B, jB)] - s.xs[t * 4 + B];
+  float rmax = fmaxf(fabsf(rA) / g.a_kick[A], fabsf(rB) / g.a_kick[B]);
+  float k = (float)f.S;
   const int Cs[2] = {C1, C2};
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int i = 0; i < 2; ++i) {
     float lo, hi;
-    completion_bounds(g, p, s, t, A, Cs[k], mA, slope, lo, hi);
-    const double xsl = s.xs[t * 4 + Cs[k]];
-    const double a = g.a_kick[Cs[k]];
-    const double r = fmax(fabs((double)lo - xsl), fabs((double)hi - xsl)) * (1.0 + 1e-6);
-    rmax = fmax(rmax, r / a);
-    kC += (double)s.wmax[t * 4 + Cs[k]] * a * a;
+    completion_bounds(g, p, s, t, A, Cs[i], mA, slope, lo, hi);
+    const float xsl = s.xs[t * 4 + Cs[i]];
+    const float a = g.a_kick[Cs[i]];
+    rmax = fmaxf(rmax, fmaxf(fabsf(lo - xsl), fabsf(hi - xsl)) / a);
+    k += s.wmax[t * 4 + Cs[i]] * a * a;
   }
-  return rmax * sqrt(f.S + kC);
+  return rmax * sqrtf(k) * 1.001f;
 }
 
 // Completion hits of layer Cl (mask m) that can still be in a selected candidate, given U.
 __device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
-                                      const AnchorFit& f, double Z, double U) {
-  constexpr double u = 5.9604644775390625e-08;   // 2^-24
-  const double E = 7.0 * u * (2.0 * U + 1.0) + 2.02 * u * sqrt(2.0 * U + 1.0) * Z;
-  if (!(E <= U + 1.0) || !isfinite(f.chi2ab)) return m;   // premises fail: keep all
-  const double room = (U + 4.0 * E + 1e-6 * (U + 1.0)) - f.chi2ab;
-  if (room < 0.0) return 0u;
+                                      const AnchorFit& f, float Z, float U) {
+  constexpr float u = 5.9604644775390625e-08f;   // 2^-24
+  const float E = (7.0f * u * (2.0f * U + 1.0f) + 2.02f * u * sqrtf(2.0f * U + 1.0f) * Z) * 1.001f;
+  if (!(E <= U + 1.0f) || !isfinite(f.C)) return m;   // premises fail: keep all
+  const double T = (double)U + 4.0 * (double)E + 1e-6 * ((double)U + 1.0);
+  const double S2 = f.S * f.S;
+  if (f.C > T * S2) return 0u;   // chi2_AB alone exceeds the bound
   const double a = g.a_kick[Cl];
   const float xsl = s.xs[t * 4 + Cl];
   uint32_t keep = 0;
   for (uint32_t mm = m; mm; mm &= mm - 1) {
     const uint32_t j = (uint32_t)__builtin_ctz(mm);
     const int o = tile_at(t, Cl, (int)j);
-    const float r = s.tm[o] - xsl;
+    const double r = (double)(s.tm[o] - xsl);
     const double w = s.tw[o];
-    const double e = (double)r - a * f.qab;
-    if (f.S * w * e * e <= room * (f.S + w * a * a) * (1.0 + 1e-12)) keep |= 1u << j;
+    const double k = w * a * a;
+    const double e = r * f.S - a * f.N;
+    const double lhs = f.C * (f.S + k) + f.S * w * e * e;
+    if (lhs <= T * S2 * (f.S + k) * (1.0 + 1e-12)) keep |= 1u << j;
   }
   return keep;
 }
 
-// Window slot of the hit of mask m in layer Cl nearest (weighted) to the two-anchor fit.
+// Window slot of the hit of mask m in layer Cl nearest (weighted) to the two-anchor fit
+// (approximate arithmetic: the choice only steers the pruning).
 __device__ inline uint32_t nearest_slot(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
-                                        double qab) {
-  const double a = g.a_kick[Cl];
+                                        float qab) {
+  const float a = g.a_kick[Cl];
   const float xsl = s.xs[t * 4 + Cl];
-  double best = 0.0;
+  float best = 0.0f;
   uint32_t arg = 0;
   bool any = false;
   for (uint32_t mm = m; mm; mm &= mm - 1) {
     const uint32_t j = (uint32_t)__builtin_ctz(mm);
     const int o = tile_at(t, Cl, (int)j);
-    const double e = (double)(s.tm[o] - xsl) - a * qab;
-    const double sc = (double)s.tw[o] * e * e;
+    const float e = (s.tm[o] - xsl) - a * qab;
+    const float sc = s.tw[o] * e * e;
     if (!any || sc < best) { best = sc; arg = j; any = true; }
   }
   return arg;
@@ -318,7 +328,13 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     m1 = completion_range(g, p, s, tt, A, C1, mA, slope) & s.umask[tt * 4 + C1];
     m2 = completion_range(g, p, s, tt, A, C2, mA, slope) & s.umask[tt * 4 + C2];
   }
+  // pruning pays for itself only when the batch has many 4-hit candidates
+  uint32_t full_tot = 0;
   if (nhits == 4 && p.prune) {
+    const uint32_t full = (uint32_t)lane < np ? (uint32_t)(__popc(m1) * __popc(m2)) : 0u;
+    full_tot = wave_sum(full);
+  }
+  if (nhits == 4 && p.prune && full_tot > (uint32_t)kPruneMinCandidates) {
     // one seed per track and batch: the pair with the lowest two-anchor chi2, with the completion
     // hits nearest to its fit; the seed's chi2 bounds the rest of the track's candidates
     const bool multi = (uint32_t)lane < np && m1 && m2 && __popc(m1) * __popc(m2) > 1;
@@ -327,7 +343,8 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     wave_sync();
     if (multi) {
       af = anchor_fit(g, s, tt, A, B, jA, jB);
-      atomicMin(&s.lbk[tt], ((unsigned long long)__float_as_uint((float)af.chi2ab) << 32) | (unsigned)lane);
+      const float c2ab = __fdividef((float)af.C, (float)(af.S * af.S));
+      atomicMin(&s.lbk[tt], ((unsigned long long)__float_as_uint(fabsf(c2ab)) << 32) | (unsigned)lane);
     }
     wave_sync();
     if (multi && (uint32_t)(s.lbk[tt] & 0xFFFFFFFFull) == (uint32_t)lane) {
@@ -343,11 +360,11 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     wave_sync();
     if (multi) {
       const unsigned long long bk = s.best[tt];
-      const double U = (double)__uint_as_float((uint32_t)(bk >> 24));
+      const float U = __uint_as_float((uint32_t)(bk >> 24));
       if (bk != kNoKey && isfinite(U)) {
         const float mA = s.tm[tile_at(tt, A, jA)];
         const float slope = (s.tm[tile_at(tt, B, jB)] - mA) * inv_dz_ab;
-        const double Z = pair_z(g, p, s, tt, A, B, C1, C2, jA, jB, mA, slope, af);
+        const float Z = pair_z(g, p, s, tt, A, B, C1, C2, jA, jB, mA, slope, af);
         if (isfinite(Z)) {
           m1 = prune_mask(g, s, tt, C1, m1, af, Z, U);
           m2 = m1 ? prune_mask(g, s, tt, C2, m2, af, Z, U) : 0u;
@@ -478,10 +495,27 @@ struct TrackIO {
 };
 
 // The whole search for tracks [tbase, min(tbase+16, t1)) of one event.
+// VELO state of the track of this lane in the group starting at tbase (zeros past t1).
+struct LaneState {
+  float x0, y0, tx, ty;
+};
+
+__device__ inline LaneState load_state(const TrackIO& io, uint32_t tbase, uint32_t t1) {
+  const uint32_t trk = tbase + (uint32_t)(lane_id() >> 2);
+  LaneState st{0.0f, 0.0f, 0.0f, 0.0f};
+  if (trk < t1) {
+    st.x0 = io.vx[trk];
+    st.y0 = io.vy[trk];
+    st.tx = io.vtx[trk];
+    st.ty = io.vty[trk];
+  }
+  return st;
+}
+
 template <bool kULds, bool kWLds>
 __device__ inline void compass_group(const Geom& g, const CPar& p, const EventView& ev,
                                      const GroupScratch& s, uint32_t tbase, uint32_t t1,
-                                     const TrackIO& io)
+                                     const TrackIO& io, const LaneState& st)
 {
   const int lane = lane_id();
   const int t = lane >> 2, l = lane & 3;
@@ -489,13 +523,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   const int M = p.max_hits;
   const uint32_t trk = tbase + (uint32_t)t;
   const bool has = trk < t1;
-  float x0 = 0.0f, y0 = 0.0f, tx = 0.0f, ty = 0.0f;
-  if (has) {
-    x0 = io.vx[trk];
-    y0 = io.vy[trk];
-    tx = io.vtx[trk];
-    ty = io.vty[trk];
-  }
+  const float x0 = st.x0, y0 = st.y0, tx = st.tx, ty = st.ty;
   // straight-line extrapolation of the VELO state to this lane's layer
   const float dz = g.z_layer[l] - g.z_velo;
   const float xs = x0 + tx * dz;
@@ -519,8 +547,21 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
     const int s_hi = c + p.half > S - 1 ? S - 1 : c + p.half;
     const uint32_t H0 = ev.hoff[l * S + s_lo], H1 = ev.hoff[l * S + s_hi + 1];
     const float lo = up - p.W, hi = up + p.W;
-    uint32_t first = first_true_u32(H0, H1, [&](uint32_t k) { return ev_u<kULds>(ev, k) >= lo; });
-    uint32_t end = first_true_u32(first, H1, [&](uint32_t k) { return ev_u<kULds>(ev, k) > hi; });
+    // both edges in one loop (two independent searches over [H0, H1), loads issued together)
+    uint32_t a0 = H0, a1 = H1, b0 = H0, b1 = H1;
+    while (a0 < a1 || b0 < b1) {
+      const uint32_t am = a0 + ((a1 - a0) >> 1), bm = b0 + ((b1 - b0) >> 1);
+      const float ua = a0 < a1 ? ev_u<kULds>(ev, am) : 0.0f;
+      const float ub = b0 < b1 ? ev_u<kULds>(ev, bm) : 0.0f;
+      if (a0 < a1) {
+        if (ua >= lo) a1 = am; else a0 = am + 1;
+      }
+      if (b0 < b1) {
+        if (ub > hi) b1 = bm; else b0 = bm + 1;
+      }
+    }
+    uint32_t first = a0;
+    uint32_t end = b0 < first ? first : b0;
     if (end - first > (uint32_t)M) {
       // the M nearest hits: the first start f whose left hit is no farther than the hit just past
       // the window (identical to dropping the farther end one hit at a time, the right on a tie)
@@ -542,10 +583,10 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   const float g_yb = g.y_begin, g_ye = g.y_end;
   uint32_t umask = 0;
   float wm = 0.0f;
-  for (int j0 = 0; j0 < wn; j0 += 4) {
-    float uu[4], ww[4], yb[4], ye[4];
+  for (int j0 = 0; j0 < wn; j0 += 8) {
+    float uu[8], ww[8], yb[8], ye[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const uint32_t k = wf + (uint32_t)(j0 + q);
       const bool in = j0 + q < wn;
       uu[q] = 0.0f;
@@ -562,7 +603,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       if (j0 + q < wn) {
         const float w = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
         s.tm[tile_at(t, l, j0 + q)] = uu[q] + yl * g.dxdy[l];
