@@ -151,17 +151,12 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
     if (!(geom->a_kick[l] > 0.0f) || !std::isfinite(geom->a_kick[l])) p.prune = 0;
   const int block = launch ? launch->block : 256;
   const int waves = block / kWave;
-  // stage u of events up to u_cap hits, keeping the workgroup's LDS within its share of the CU's
-  // 160 KiB at the occupancy the kernel's registers allow; larger events search global memory
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_compass, block, 0) != hipSuccess || per_cu < 1) {
-    (void)hipGetLastError();
-    per_cu = 1;
-  }
-  const size_t budget = (size_t)160 * 1024 / (size_t)per_cu;
+  // stage u of events up to u_cap hits, keeping the workgroup's LDS at 10 KiB per wavefront (four
+  // 256-thread workgroups share a CU's 160 KiB, the occupancy the kernel's registers allow);
+  // larger events search global memory
+  const size_t budget = (size_t)waves * 10 * 1024;
   const size_t fixed = compass_lds_bytes(g.S, p.max_hits, waves, 0);
-  int u_cap = fixed < budget ? (int)((budget - fixed) / sizeof(float)) / 64 * 64 : 0;
-  if (u_cap > 1 << 20) u_cap = 1 << 20;
+  const int u_cap = fixed < budget ? (int)((budget - fixed) / sizeof(float)) / 64 * 64 : 0;
   const size_t lds = compass_lds_bytes(g.S, p.max_hits, waves, u_cap);
   if (lds > 160 * 1024) return UTC_ERR_ARG;
   (void)hipGetLastError();  // report only errors of this call

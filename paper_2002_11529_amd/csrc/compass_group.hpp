@@ -72,11 +72,12 @@ struct GroupScratch {
   uint32_t* bm1;      // [64] their completion masks in layer C1
   uint32_t* bm2;      // [64] their completion masks in layer C2
   uint32_t* boff;     // [65] candidate offsets of the batch
+  uint32_t* mk;       // [64] pair starting at each candidate slot of a chunk (index + 1, 0 = none)
 };
 
 __host__ __device__ inline size_t group_scratch_bytes(int max_hits) {
   const size_t b = 16 * kGroupTracks + 8 * 64 + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
-                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65;
+                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65 + 4 * 64;
   return (b + 15) / 16 * 16;
 }
 
@@ -96,6 +97,7 @@ __device__ inline GroupScratch carve_group(char* p, int max_hits) {
   s.bm1 = s.bp + 64;
   s.bm2 = s.bm1 + 64;
   s.boff = s.bm2 + 64;
+  s.mk = s.boff + 65;
   return s;
 }
 
@@ -384,11 +386,21 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
   s.boff[lane] = coff;
   if (lane == 0) s.boff[kWave] = ctot;
   wave_sync();
-  // candidates of the batch, one per lane
+  // candidates of the batch, one per lane; the pair of each candidate slot of a chunk is the last
+  // pair starting at or before it (markers at the pairs' first slots, then a running maximum)
+  const bool has_cand = ncand > 0u;
   for (uint32_t cb = 0; cb < ctot; cb += kWave) {
+    s.mk[lane] = 0u;
+    wave_sync();
+    if (has_cand && coff >= cb && coff < cb + (uint32_t)kWave) s.mk[coff - cb] = (uint32_t)lane + 1u;
+    const uint64_t before = ballot(has_cand && coff <= cb);   // pairs starting at or before the chunk
+    wave_sync();
+    uint32_t m = s.mk[lane];
+    if (lane == 0 && before) m = max(m, (uint32_t)(63 - __builtin_clzll(before)) + 1u);
+    const uint32_t pi1 = wave_inclusive_max(m);
     const uint32_t ci = cb + (uint32_t)lane;
     if (ci < ctot) {
-      const uint32_t pi = first_true_u32(0u, np, [&](uint32_t k) { return s.boff[k + 1] > ci; });
+      const uint32_t pi = pi1 - 1u;
       const uint32_t rr = ci - s.boff[pi];
       const uint32_t c1m = s.bm1[pi], c2m = s.bm2[pi];
       uint32_t k1, k2;  // window slot + 1 of the completion hits, 0 = none
