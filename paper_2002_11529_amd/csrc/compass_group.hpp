@@ -170,19 +170,25 @@ __device__ inline uint32_t range_mask(uint32_t lo, uint32_t hi) {
 __device__ inline uint32_t slope_range(const GroupScratch& s, int t, int B, float mA, float inv_dz,
                                        float tx, float tol) {
   const uint32_t n = (uint32_t)s.nwin[t * 4 + B];
-  auto dev = [&](uint32_t j) { return (s.tm[tile_at(t, B, (int)j)] - mA) * inv_dz - tx; };
-  uint32_t lo, hi;
-  if (inv_dz >= 0.0f) {
-    lo = first_true_u32(0u, n, [&](uint32_t j) { return dev(j) >= -tol; });
-    hi = first_true_u32(lo, n, [&](uint32_t j) { return dev(j) > tol; });
-  } else {
-    lo = first_true_u32(0u, n, [&](uint32_t j) { return dev(j) <= tol; });
-    hi = first_true_u32(lo, n, [&](uint32_t j) { return dev(j) < -tol; });
+  // both ends searched in one loop over [0, n) (independent searches, loads issued together); with
+  // dz < 0 the deviation decreases along the slots and the two tests swap roles
+  const bool up = inv_dz >= 0.0f;
+  uint32_t a0 = 0, a1 = n, b0 = 0, b1 = n;
+  while (a0 < a1 || b0 < b1) {
+    const uint32_t am = a0 + ((a1 - a0) >> 1), bm = b0 + ((b1 - b0) >> 1);
+    const float da = a0 < a1 ? (s.tm[tile_at(t, B, (int)am)] - mA) * inv_dz - tx : 0.0f;
+    const float db = b0 < b1 ? (s.tm[tile_at(t, B, (int)bm)] - mA) * inv_dz - tx : 0.0f;
+    if (a0 < a1) {
+      if (up ? (da >= -tol) : (da <= tol)) a1 = am; else a0 = am + 1;
+    }
+    if (b0 < b1) {
+      if (up ? (db > tol) : (db < -tol)) b1 = bm; else b0 = bm + 1;
+    }
   }
-  return range_mask(lo, hi);
+  return range_mask(a0, b0);
 }
 
-// Completion interval of layer Cl for a pair (the one completion_range searches).
+// Completion interval of layer Cl for a pair (the one completion_ranges searches).
 __device__ inline void completion_bounds(const Geom& g, const CPar& p, const GroupScratch& s, int t,
                                          int A, int Cl, float mA, float slope, float& lo, float& hi) {
   const float d = g.z_layer[Cl] - g.z_layer[A];
@@ -194,14 +200,32 @@ __device__ inline void completion_bounds(const Geom& g, const CPar& p, const Gro
 
 // Completion slots of a passing pair in layer Cl: x inside the interval spanned by the pair-slope
 // and VELO-slope extrapolations from the first anchor, widened by the completion tolerance.
-__device__ inline uint32_t completion_range(const Geom& g, const CPar& p, const GroupScratch& s,
-                                            int t, int A, int Cl, float mA, float slope) {
-  float lo, hi;
-  completion_bounds(g, p, s, t, A, Cl, mA, slope, lo, hi);
-  const uint32_t n = (uint32_t)s.nwin[t * 4 + Cl];
-  const uint32_t a = first_true_u32(0u, n, [&](uint32_t j) { return s.tm[tile_at(t, Cl, (int)j)] >= lo; });
-  const uint32_t b = first_true_u32(a, n, [&](uint32_t j) { return s.tm[tile_at(t, Cl, (int)j)] > hi; });
-  return range_mask(a, b);
+// Completion slots of a passing pair in both completion layers; the four range ends are searched
+// in one loop (independent searches, loads issued together).  In each layer the slots with
+// x > hi are a subset of those with x >= lo unless the interval is empty, in which case the mask
+// comes out empty either way.
+__device__ inline void completion_ranges(const Geom& g, const CPar& p, const GroupScratch& s, int t,
+                                         int A, int C1, int C2, float mA, float slope, uint32_t& m1,
+                                         uint32_t& m2) {
+  float lo1, hi1, lo2, hi2;
+  completion_bounds(g, p, s, t, A, C1, mA, slope, lo1, hi1);
+  completion_bounds(g, p, s, t, A, C2, mA, slope, lo2, hi2);
+  const uint32_t n1 = (uint32_t)s.nwin[t * 4 + C1], n2 = (uint32_t)s.nwin[t * 4 + C2];
+  uint32_t a0 = 0, a1 = n1, b0 = 0, b1 = n1, c0 = 0, c1 = n2, d0 = 0, d1 = n2;
+  while (a0 < a1 || b0 < b1 || c0 < c1 || d0 < d1) {
+    const uint32_t am = a0 + ((a1 - a0) >> 1), bm = b0 + ((b1 - b0) >> 1);
+    const uint32_t cm = c0 + ((c1 - c0) >> 1), dm = d0 + ((d1 - d0) >> 1);
+    const float xa = a0 < a1 ? s.tm[tile_at(t, C1, (int)am)] : 0.0f;
+    const float xb = b0 < b1 ? s.tm[tile_at(t, C1, (int)bm)] : 0.0f;
+    const float xc = c0 < c1 ? s.tm[tile_at(t, C2, (int)cm)] : 0.0f;
+    const float xd = d0 < d1 ? s.tm[tile_at(t, C2, (int)dm)] : 0.0f;
+    if (a0 < a1) { if (xa >= lo1) a1 = am; else a0 = am + 1; }
+    if (b0 < b1) { if (xb > hi1) b1 = bm; else b0 = bm + 1; }
+    if (c0 < c1) { if (xc >= lo2) c1 = cm; else c0 = cm + 1; }
+    if (d0 < d1) { if (xd > hi2) d1 = dm; else d0 = dm + 1; }
+  }
+  m1 = range_mask(a0, b0);
+  m2 = range_mask(c0, d0);
 }
 
 // Exact pruning of the 4-hit candidates of one passing anchor pair.
@@ -327,8 +351,9 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     const float mA = s.tm[tile_at(tt, A, jA)];
     const float mB = s.tm[tile_at(tt, B, jB)];
     const float slope = (mB - mA) * inv_dz_ab;
-    m1 = completion_range(g, p, s, tt, A, C1, mA, slope) & s.umask[tt * 4 + C1];
-    m2 = completion_range(g, p, s, tt, A, C2, mA, slope) & s.umask[tt * 4 + C2];
+    completion_ranges(g, p, s, tt, A, C1, C2, mA, slope, m1, m2);
+    m1 &= s.umask[tt * 4 + C1];
+    m2 &= s.umask[tt * 4 + C2];
   }
   // pruning pays for itself only when the batch has many 4-hit candidates
   uint32_t full_tot = 0;
@@ -450,9 +475,17 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
     const uint32_t it = base + (uint32_t)lane;
     uint32_t rem = 0;    // anchor-B slots still to be paired with this lane's anchor-A hit
     uint32_t head = 0;   // track | anchor-A slot << 8
+    // track of each item: markers at the tracks' first items, then a running maximum
+    s.mk[lane] = 0u;
+    wave_sync();
+    if (l == 0 && cnt > 0u && off >= base && off < base + (uint32_t)kWave) s.mk[off - base] = (uint32_t)t + 1u;
+    const uint64_t before = ballot(l == 0 && cnt > 0u && off <= base);
+    wave_sync();
+    uint32_t mtr = s.mk[lane];
+    if (lane == 0 && before) mtr = max(mtr, (uint32_t)((63 - __builtin_clzll(before)) >> 2) + 1u);
+    const uint32_t tr1 = wave_inclusive_max(mtr);
     if (it < total) {
-      const int tt = (int)first_true_u32(0u, (uint32_t)kGroupTracks,
-                                         [&](uint32_t k) { return s.poff[k + 1] > it; });
+      const int tt = (int)tr1 - 1;
       const uint32_t jA = it - s.poff[tt];
       head = (uint32_t)tt | (jA << 8);
       if ((s.umask[tt * 4 + A] >> jA) & 1u) {
