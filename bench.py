@@ -35,11 +35,16 @@ KERNEL_SOURCES = {
 
 
 def kernel_source_hash(kernel):
+    """Hash of the code (comments and whitespace removed) of the sources a kernel is built from."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

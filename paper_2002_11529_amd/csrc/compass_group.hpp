@@ -1,12 +1,13 @@
-// Compass tracklet search for a group of 16 VELO tracks by one wavefront (Section V of the paper):
-// the device code shared by the stand-alone compass_find kernel and the fused kernel.
+// Compass tracklet search for a group of 16 VELO tracks by one wavefront (Section V of the paper).
 //
 // Lane layout for windows: lane = 4*t + l (track t of the group, layer l).  Each lane extrapolates
 // its track to its layer, does the binary searches for its window and copies the window's hits
 // (x at the track's y, weight or -1 when the strip does not cover the track's y) into an LDS tile.
-// Tracklets: the (anchor A, anchor B) pairs of all 16 tracks are flattened over the lanes; each
-// lane tests its pair's slope, builds the completion masks, fits every candidate and folds the
-// candidate's 64-bit selection key into the track's minimum with an LDS atomic.  The key orders
+// Tracklets: the work items (track, anchor-A hit) are spread over the lanes; each finds its passing
+// anchor-B hits as a slot range, the passing pairs are handed out in batches of at most 64, each
+// pair's completion hits are found as slot ranges, the 4-hit candidates are pruned exactly against
+// a seed (see run_batch), and the remaining candidates are flattened over the lanes, fitted, and
+// their 64-bit selection keys folded into the track's minimum with an LDS atomic.  The key orders
 // candidates exactly like the reference selection (more hits, then lower chi2, then the
 // lexicographically smaller hit-index tuple), so the minimum is the same for every schedule.
 #pragma once

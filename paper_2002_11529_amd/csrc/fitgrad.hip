@@ -4,8 +4,8 @@
 // function of the per-sector x offsets delta and the per-track q/p.  One thread per track computes
 // its chi2 and d chi2/d qop directly; the per-sector sums of w*r and the total chi2 are accumulated
 // exactly as integers in units of 2^-40 (a hi/lo pair of 64-bit words per sum), first in LDS per
-// workgroup and then with one global atomic per workgroup and sector, so the result is the same
-// for every schedule and launch shape.
+// workgroup, then as one column of partial sums per workgroup that a second kernel adds up, so the
+// result is the same for every schedule and launch shape.
 #include "common.hpp"
 
 namespace utc {
