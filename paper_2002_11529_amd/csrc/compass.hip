@@ -49,19 +49,22 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     for (int l = 0; l < kLayers; ++l)
       if (s_hoff[(l + 1) * S] - s_hoff[l * S] > 32767u) overflow = true;
     const bool staged = nh <= (uint32_t)u_cap;
-    if (staged) {
-      for (uint32_t k0 = 0; k0 < nh; k0 += 8 * bs) {
-        float v[8];
+    // u of every hit when the event fits, else of every stride-th hit (a coarse index for the
+    // window searches, which then finish with a few steps in global memory)
+    uint32_t stride = 1;
+    while (u_cap > 0 && (nh + stride - 1) / stride > (uint32_t)u_cap) stride *= 2;
+    const uint32_t ncoarse = u_cap > 0 ? (nh + stride - 1) / stride : 0u;
+    for (uint32_t k0 = 0; k0 < ncoarse; k0 += 8 * bs) {
+      float v[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t k = k0 + q * bs + tid;
-          v[q] = k < nh ? hu[(int64_t)H + k] : 0.0f;
-        }
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t k = k0 + q * bs + tid;
+        v[q] = k < ncoarse ? hu[(int64_t)H + (int64_t)k * stride] : 0.0f;
+      }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const uint32_t k = k0 + q * bs + tid;
-          if (k < nh) s_u[k] = v[q];
-        }
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t k = k0 + q * bs + tid;
+        if (k < ncoarse) s_u[k] = v[q];
       }
     }
     if (overflow && tid == 0) raise_flag(flags, UTC_FLAG_LAYER_OVERFLOW);
@@ -76,6 +79,7 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     ev.hoff = s_hoff;
     ev.first = H;
     ev.overflow = overflow;
+    ev.stride = staged ? 1u : (ncoarse > 0 ? stride : 0u);
     const uint32_t t0 = velo_offsets[e], t1 = velo_offsets[e + 1];
     const uint32_t ngroups = (t1 - t0 + kGroupTracks - 1) / kGroupTracks;
     // the next group's VELO states are loaded while the current group is searched

@@ -42,6 +42,7 @@ struct EventView {
   const uint32_t* hoff;        // [4S+1] event-local first hit of each bank
   int64_t first;               // global index of the event's first hit
   bool overflow;               // an (event, layer) holds more than 32767 hits
+  uint32_t stride;             // u_lds[k] = u of hit k*stride (1: every hit; 0: nothing staged)
 };
 
 template <bool kULds>
@@ -593,8 +594,30 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
     const int s_hi = c + p.half > S - 1 ? S - 1 : c + p.half;
     const uint32_t H0 = ev.hoff[l * S + s_lo], H1 = ev.hoff[l * S + s_hi + 1];
     const float lo = up - p.W, hi = up + p.W;
-    // both edges in one loop (two independent searches over [H0, H1), loads issued together)
+    // both edges in one loop (two independent searches over [H0, H1), loads issued together);
+    // with a coarse index in LDS the searches first narrow each edge to less than one stride
     uint32_t a0 = H0, a1 = H1, b0 = H0, b1 = H1;
+    if (!kULds && ev.stride > 1u && H1 > H0) {
+      const uint32_t st = ev.stride;
+      const uint32_t c_lo = (H0 + st - 1) / st, c_hi = (H1 - 1) / st + 1;   // coarse entries in [H0, H1)
+      uint32_t ca0 = c_lo, ca1 = c_hi, cb0 = c_lo, cb1 = c_hi;
+      while (ca0 < ca1 || cb0 < cb1) {
+        const uint32_t am = ca0 + ((ca1 - ca0) >> 1), bm = cb0 + ((cb1 - cb0) >> 1);
+        const float ua = ca0 < ca1 ? ev.u_lds[am] : 0.0f;
+        const float ub = cb0 < cb1 ? ev.u_lds[bm] : 0.0f;
+        if (ca0 < ca1) {
+          if (ua >= lo) ca1 = am; else ca0 = am + 1;
+        }
+        if (cb0 < cb1) {
+          if (ub > hi) cb1 = bm; else cb0 = bm + 1;
+        }
+      }
+      // the first true hit lies after the last false coarse entry and at or before the first true one
+      if (ca0 > c_lo) a0 = (ca0 - 1) * st + 1;
+      if (ca0 < c_hi) a1 = ca0 * st;
+      if (cb0 > c_lo) b0 = (cb0 - 1) * st + 1;
+      if (cb0 < c_hi) b1 = cb0 * st;
+    }
     while (a0 < a1 || b0 < b1) {
       const uint32_t am = a0 + ((a1 - a0) >> 1), bm = b0 + ((b1 - b0) >> 1);
       const float ua = a0 < a1 ? ev_u<kULds>(ev, am) : 0.0f;
