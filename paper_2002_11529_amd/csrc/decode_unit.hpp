@@ -88,6 +88,33 @@ __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict
     const uint32_t nw = ws.off[S] - w0;
     st.staged = ws.raw != nullptr && nw <= (uint32_t)kCap;
     uint32_t c = 0;
+    if ((reinterpret_cast<uintptr_t>(words) & 15u) == 0) {
+      // 16-byte loads of 8 words per lane from the aligned word at or before w0
+      const uint32_t a0 = w0 & ~7u;
+      const uint32_t span = w0 + nw - a0;
+      for (uint32_t j0 = 0; j0 < span; j0 += 8 * 2 * kWave) {
+        uint4 v[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t j = j0 + 8 * (k * kWave + lane);
+          v[k] = j < span ? *reinterpret_cast<const uint4*>(words + a0 + j) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t j = j0 + 8 * (k * kWave + lane);
+          const uint32_t parts[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+          for (int h = 0; h < 8; ++h) {
+            const uint32_t word = (parts[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
+            const uint32_t g = a0 + j + (uint32_t)h;   // absolute word index
+            if (g >= w0 && g < w0 + nw) {
+              if (st.staged) ws.raw[g - w0] = (uint16_t)word;
+              c += (word & 0xFu) != 0u;
+            }
+          }
+        }
+      }
+    } else
     for (uint32_t i0 = 0; i0 < nw; i0 += 8 * kWave) {
       uint16_t v[8];
 #pragma unroll
