@@ -66,7 +66,19 @@ __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict
 {
   const int S = g.S;
   const int lane = lane_id();
-  for (int s = lane; s <= S; s += kWave) ws.off[s] = bank_offsets[b0 + s];
+  for (int s0 = 0; s0 <= S; s0 += 4 * kWave) {
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int s = s0 + k * kWave + lane;
+      v[k] = s <= S ? bank_offsets[b0 + s] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int s = s0 + k * kWave + lane;
+      if (s <= S) ws.off[s] = v[k];
+    }
+  }
   wave_sync();
   bool bad = false;
   for (int s = lane; s < S; s += kWave) {
@@ -245,7 +257,29 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       continue;
     }
     const uint32_t n = ws.off[c1] - a0;
-    if (!st.staged) {
+    if (!st.staged && (reinterpret_cast<uintptr_t>(words) & 15u) == 0) {
+      // 16-byte loads of 8 words per lane from the aligned word at or before a0
+      const uint32_t al = a0 & ~7u;
+      const uint32_t span = a0 + n - al;
+      for (uint32_t j0 = 0; j0 < span; j0 += 8 * 2 * kWave) {
+        uint4 v[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t j = j0 + 8 * (k * kWave + lane);
+          v[k] = j < span ? *reinterpret_cast<const uint4*>(words + al + j) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t j = j0 + 8 * (k * kWave + lane);
+          const uint32_t parts[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+          for (int h = 0; h < 8; ++h) {
+            const uint32_t gi = al + j + (uint32_t)h;
+            if (gi >= a0 && gi < a0 + n) ws.raw[gi - a0] = (uint16_t)((parts[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
+          }
+        }
+      }
+    } else if (!st.staged) {
       for (uint32_t i0 = 0; i0 < n; i0 += 8 * kWave) {
         uint16_t v[8];
 #pragma unroll
