@@ -287,11 +287,57 @@ def main():
         "found_fraction": round(n_found / max(Nt, 1), 5),
         "wall_s": round(wall, 4),
     }
+    out["event_cut_and_consolidation"] = bench_select(args, b, geom, copies[0], E, S)
     if not args.no_fitgrad:
         out["fitgrad"] = bench_fitgrad(args, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_select(args, b, geom, c, E, S):
+    """The steps either side of the chain on the benchmark batch: the global event cut (limit at
+    the 90th percentile of the raw words per event) and the consolidation of the found tracks."""
+    import numpy as np
+    import torch
+
+    import paper_2002_11529_amd as utc
+
+    per_event = np.diff(b.bank_offsets[::4 * S].astype(np.int64))
+    limit = int(np.percentile(per_event, 90))
+    L = utc.library()
+    ws_cut = torch.empty(L.ut_global_event_cut_workspace_bytes(E), dtype=torch.uint8, device=c["words"].device)
+    cut = utc.ut_global_event_cut(geom, E, c["words"], c["boff"], *c["vel"], c["vo"], limit, workspace=ws_cut)
+    ws_cons = torch.empty(L.compass_consolidate_workspace_bytes(b.n_tracks), dtype=torch.uint8,
+                          device=c["words"].device)
+    cons = utc.compass_consolidate(E, c["vo"], c["res"], workspace=ws_cons)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_cut = timed(lambda: utc.ut_global_event_cut(geom, E, c["words"], c["boff"], *c["vel"], c["vo"], limit,
+                                                   out=cut, workspace=ws_cut))
+    ms_cons = timed(lambda: utc.compass_consolidate(E, c["vo"], c["res"], out=cons, workspace=ws_cons))
+    kept = int(cut["n_kept"].item())
+    kw = int(cut["bank_offsets"][-1].item())
+    kt = int(cut["velo_offsets"][-1].item())
+    nf = int(cons["n_found"].item())
+    nb = E * 4 * S
+    bytes_cut = 2 * (2 * kw + 16 * kt) + 2 * 4 * (nb + 1) + 2 * 4 * (E + 1) + E
+    bytes_cons = 4 * b.n_tracks + nf * (24 + 32) + 4 * (E + 1) * 2
+    return {"event_cut": {"ms": round(ms_cut, 5), "max_words": limit, "kept_events": kept,
+                          "algorithmic_GBps": round(bytes_cut / (ms_cut * 1e-3) / 1e9, 1)},
+            "consolidation": {"ms": round(ms_cons, 5), "found_tracks": nf,
+                              "algorithmic_GBps": round(bytes_cons / (ms_cons * 1e-3) / 1e9, 1)}}
 
 
 def copy_calibration():

@@ -182,6 +182,55 @@ utc_status compass_find_autotune(const utc_geometry* geom, const utc_compass_par
                                  size_t workspace_bytes, int32_t reps, utc_launch_config* best,
                                  float* best_us, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * ut_global_event_cut — the global event cut that precedes decoding (Section VI: events are
+ * selected before the UT chain runs).  An event is kept when its raw banks hold at most max_words
+ * words in total (padding included); kept events are copied, in order, into a compact batch of the
+ * same n_events events in which every rejected event is empty (no words, no VELO tracks), so the
+ * following ut_decode / compass_find calls take the same event count and need no host round trip.
+ *
+ * Inputs: the raw-bank batch of ut_decode (words, bank_offsets [n_events*4*S + 1]) and the VELO
+ * states of compass_find (vx, vy, vtx, vty, velo_offsets [n_events + 1]).
+ * Outputs: out_words (capacity: bank_offsets[n_events*4*S] words), out_bank_offsets
+ * [n_events*4*S + 1], out_vx/vy/vtx/vty (capacity: velo_offsets[n_events]), out_velo_offsets
+ * [n_events + 1], keep [n_events] (1 kept, 0 rejected; may be NULL), n_kept (device int32, the
+ * number of kept events; may be NULL).  Output arrays must not overlap the inputs.
+ * Bank offsets that decrease are treated as an empty event (and flagged UTC_FLAG_BANK_ORDER).
+ * Workspace: ut_global_event_cut_workspace_bytes(n_events) bytes, any content.
+ * --------------------------------------------------------------------------------------------- */
+size_t ut_global_event_cut_workspace_bytes(int32_t n_events);
+
+utc_status ut_global_event_cut(const utc_geometry* geom, int32_t n_events, const uint16_t* words,
+                               const uint32_t* bank_offsets, const float* vx, const float* vy,
+                               const float* vtx, const float* vty, const uint32_t* velo_offsets,
+                               uint32_t max_words, uint16_t* out_words, uint32_t* out_bank_offsets,
+                               float* out_vx, float* out_vy, float* out_vtx, float* out_vty,
+                               uint32_t* out_velo_offsets, uint8_t* keep, int32_t* n_kept,
+                               uint32_t* error_flags, void* workspace, size_t workspace_bytes,
+                               hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * compass_consolidate — the found upstream tracks of compass_find gathered into a dense container
+ * (the prefix sum and consolidation step that follows the tracking, Section VI): the tracks with
+ * nhits > 0, in VELO order, with per-event offsets.
+ *
+ * Inputs: velo_offsets [n_events + 1] and compass_find's per-track outputs nhits [n_tracks],
+ * hit_idx [n_tracks*4], qop, chi2 [n_tracks].
+ * Outputs (capacity n_tracks each; only the first *n_found entries are written): out_velo
+ * (the VELO index of each found track), out_hit_idx [*4], out_qop, out_chi2, out_nhits; and
+ * out_offsets [n_events + 1], out_offsets[e] = number of found tracks in events before e
+ * (out_offsets[n_events] = *n_found); n_found (device int32; may be NULL).
+ * Workspace: compass_consolidate_workspace_bytes(n_tracks) bytes, any content.
+ * --------------------------------------------------------------------------------------------- */
+size_t compass_consolidate_workspace_bytes(int64_t n_tracks);
+
+utc_status compass_consolidate(int32_t n_events, const uint32_t* velo_offsets, int64_t n_tracks,
+                               const int32_t* nhits, const int32_t* hit_idx, const float* qop,
+                               const float* chi2, uint32_t* out_offsets, int32_t* out_velo,
+                               int32_t* out_hit_idx, float* out_qop, float* out_chi2,
+                               int32_t* out_nhits, int32_t* n_found, void* workspace,
+                               size_t workspace_bytes, hipStream_t stream);
+
 /* Human-readable name of a status code. */
 const char* utc_status_string(int status);
 

@@ -4,9 +4,11 @@ The computation lives in libutcompass.so (hand-written HIP, C ABI in include/ut_
 package is its thin ctypes binding.  See api.py.
 """
 from .api import (Geometry, compass_params, ut_decode, compass_find, compass_fit_grad,
-                  CompassChi2Function, library, version, autotune,
+                  CompassChi2Function, library, version, autotune, ut_global_event_cut,
+                  compass_consolidate,
                   FLAG_BANK_ORDER, FLAG_CAPACITY, FLAG_LAYER_OVERFLOW, FLAG_BANK_SIZE, MAX_BANK_WORDS)
 
 __all__ = ["Geometry", "compass_params", "ut_decode", "compass_find", "compass_fit_grad",
-           "CompassChi2Function", "library", "version", "autotune", "FLAG_BANK_ORDER", "FLAG_CAPACITY",
+           "CompassChi2Function", "library", "version", "autotune", "ut_global_event_cut",
+           "compass_consolidate", "FLAG_BANK_ORDER", "FLAG_CAPACITY",
            "FLAG_LAYER_OVERFLOW", "FLAG_BANK_SIZE", "MAX_BANK_WORDS"]

@@ -78,6 +78,16 @@ def library():
     L.utc_status_string.restype = ctypes.c_char_p
     L.utc_status_string.argtypes = [ctypes.c_int]
     L.utc_version.restype = ctypes.c_char_p
+    L.ut_global_event_cut_workspace_bytes.restype = _sz
+    L.ut_global_event_cut_workspace_bytes.argtypes = [_i32]
+    L.ut_global_event_cut.restype = ctypes.c_int
+    L.ut_global_event_cut.argtypes = [_P, _i32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P, _P, _P,
+                                      _P, _P, _P, _P, _P, _P, _P, _P, _sz, _P]
+    L.compass_consolidate_workspace_bytes.restype = _sz
+    L.compass_consolidate_workspace_bytes.argtypes = [_i64]
+    L.compass_consolidate.restype = ctypes.c_int
+    L.compass_consolidate.argtypes = [_i32, _P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      _sz, _P]
     _lib = L
     return L
 
@@ -365,6 +375,60 @@ def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy,
             os.replace(tmp, path)
         except OSError:
             pass
+    return out
+
+
+def ut_global_event_cut(geom: Geometry, n_events: int, words, bank_offsets, vx, vy, vtx, vty,
+                        velo_offsets, max_words: int, error_flags=None, out=None, workspace=None,
+                        stream=None):
+    """The global event cut: a batch of the same n_events events in which the events with more than
+    max_words raw words are empty.  Returns a dict of device tensors (words, bank_offsets, vx, vy,
+    vtx, vty, velo_offsets, keep, n_kept, error_flags)."""
+    L = library()
+    dev = bank_offsets.device
+    if out is None:
+        out = dict(words=torch.empty_like(words), bank_offsets=torch.empty_like(bank_offsets),
+                   vx=torch.empty_like(vx), vy=torch.empty_like(vy), vtx=torch.empty_like(vtx),
+                   vty=torch.empty_like(vty), velo_offsets=torch.empty_like(velo_offsets),
+                   keep=torch.empty(max(n_events, 1), dtype=torch.uint8, device=dev),
+                   n_kept=torch.empty(1, dtype=torch.int32, device=dev))
+    if error_flags is None:
+        error_flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    out["error_flags"] = error_flags
+    if workspace is None:
+        workspace = _workspace(L.ut_global_event_cut_workspace_bytes(n_events), dev)
+    st = L.ut_global_event_cut(geom.ref, n_events, _ptr(words), _ptr(bank_offsets), _ptr(vx), _ptr(vy),
+                               _ptr(vtx), _ptr(vty), _ptr(velo_offsets), int(max_words), _ptr(out["words"]),
+                               _ptr(out["bank_offsets"]), _ptr(out["vx"]), _ptr(out["vy"]), _ptr(out["vtx"]),
+                               _ptr(out["vty"]), _ptr(out["velo_offsets"]), _ptr(out.get("keep")),
+                               _ptr(out.get("n_kept")), _ptr(error_flags), _ptr(workspace),
+                               workspace.numel(), _stream(stream))
+    _check(st, "ut_global_event_cut")
+    return out
+
+
+def compass_consolidate(n_events: int, velo_offsets, res, out=None, workspace=None, stream=None):
+    """The found upstream tracks (nhits > 0) of compass_find's output `res`, in VELO order, in a
+    dense container with per-event offsets.  Returns a dict of device tensors (offsets, velo,
+    hit_idx, qop, chi2, nhits, n_found); only the first n_found rows are meaningful."""
+    L = library()
+    n = int(res["nhits"].shape[0])
+    dev = res["nhits"].device
+    if out is None:
+        out = dict(offsets=torch.empty(n_events + 1, dtype=torch.int32, device=dev),
+                   velo=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                   hit_idx=torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev),
+                   qop=torch.empty(max(n, 1), dtype=torch.float32, device=dev),
+                   chi2=torch.empty(max(n, 1), dtype=torch.float32, device=dev),
+                   nhits=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                   n_found=torch.empty(1, dtype=torch.int32, device=dev))
+    if workspace is None:
+        workspace = _workspace(L.compass_consolidate_workspace_bytes(n), dev)
+    st = L.compass_consolidate(n_events, _ptr(velo_offsets), n, _ptr(res["nhits"]), _ptr(res["hit_idx"]),
+                               _ptr(res["qop"]), _ptr(res["chi2"]), _ptr(out["offsets"]), _ptr(out["velo"]),
+                               _ptr(out["hit_idx"]), _ptr(out["qop"]), _ptr(out["chi2"]), _ptr(out["nhits"]),
+                               _ptr(out.get("n_found")), _ptr(workspace), workspace.numel(), _stream(stream))
+    _check(st, "compass_consolidate")
     return out
 
 
