@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
     ap.add_argument("--no-fitgrad", action="store_true",
                     help="skip the fit-chi2 forward/backward figure on the 1e6-track workload")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the 1/3/5-sector x 1..16-candidate sweep of compass_find: events/s and the "
+                         "physics-efficiency figures on truth, one JSON line per configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     return ap.parse_args()
@@ -102,6 +105,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep:
+        sweep(args)
         return
 
     import synth
@@ -338,6 +344,46 @@ def bench_select(args, b, geom, c, E, S):
                           "algorithmic_GBps": round(bytes_cut / (ms_cut * 1e-3) / 1e9, 1)},
             "consolidation": {"ms": round(ms_cons, 5), "found_tracks": nf,
                               "algorithmic_GBps": round(bytes_cons / (ms_cons * 1e-3) / 1e9, 1)}}
+
+
+def sweep(args):
+    """compass_find over the realistic workload for 1, 3 and 5 sectors and 1 to 16 hit candidates
+    per window (the configurations of the paper's efficiency table and throughput figure)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2002_11529_amd as utc
+    from synth.efficiency import efficiency
+
+    dev = torch.device("cuda:0")
+    b = synth.generate(args.workload, n_events=args.events, with_truth=True)
+    geom = utc.Geometry(b.detector, dev)
+    words = torch.from_numpy(b.words.view(np.int16).copy()).to(dev)
+    boff = torch.from_numpy(b.bank_offsets.view(np.int32).copy()).to(dev)
+    vel = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (b.velo_x, b.velo_y, b.velo_tx, b.velo_ty)]
+    vo = torch.from_numpy(b.velo_offsets.view(np.int32).copy()).to(dev)
+    hits = utc.ut_decode(geom, words, boff, b.n_events)
+    for ns in (1, 3, 5):
+        for m in (1, 2, 4, 8, 16):
+            p = synth.make_compass_params(p_min_mev=b.params.p_min, max_hits=m, n_sectors_search=ns)
+            res = utc.compass_find(geom, p, b.n_events, hits, *vel, vo)
+            for _ in range(args.warmup):
+                utc.compass_find(geom, p, b.n_events, hits, *vel, vo, out=res)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                utc.compass_find(geom, p, b.n_events, hits, *vel, vo, out=res)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            eff = efficiency(b, res["hit_idx"].cpu().numpy(), res["nhits"].cpu().numpy())
+            print(json.dumps({"workload": args.workload, "sectors": ns, "candidates": m,
+                              "compass_find_ms": round(ms, 5),
+                              "events_per_s": round(b.n_events / (ms * 1e-3), 1),
+                              **{k: round(v, 5) if isinstance(v, float) else v for k, v in eff.items()}}),
+                  flush=True)
 
 
 def copy_calibration():
