@@ -364,26 +364,28 @@ def sweep(args):
     vel = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (b.velo_x, b.velo_y, b.velo_tx, b.velo_ty)]
     vo = torch.from_numpy(b.velo_offsets.view(np.int32).copy()).to(dev)
     hits = utc.ut_decode(geom, words, boff, b.n_events)
-    for ns in (1, 3, 5):
-        for m in (1, 2, 4, 8, 16):
-            p = synth.make_compass_params(p_min_mev=b.params.p_min, max_hits=m, n_sectors_search=ns)
-            res = utc.compass_find(geom, p, b.n_events, hits, *vel, vo)
-            for _ in range(args.warmup):
-                utc.compass_find(geom, p, b.n_events, hits, *vel, vo, out=res)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record()
-            for _ in range(args.steps):
-                utc.compass_find(geom, p, b.n_events, hits, *vel, vo, out=res)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.steps
-            eff = efficiency(b, res["hit_idx"].cpu().numpy(), res["nhits"].cpu().numpy())
-            print(json.dumps({"workload": args.workload, "sectors": ns, "candidates": m,
-                              "compass_find_ms": round(ms, 5),
-                              "events_per_s": round(b.n_events / (ms * 1e-3), 1),
-                              **{k: round(v, 5) if isinstance(v, float) else v for k, v in eff.items()}}),
-                  flush=True)
+    configs = [(v, ns, m) for v in ("exhaustive", "paper") for ns in (1, 3, 5) for m in (1, 2, 4, 8, 16)]
+    for variant, ns, m in configs:
+        # the paper's search: windows of m hits and a budget of m tracklets
+        p = synth.make_compass_params(p_min_mev=b.params.p_min, max_hits=m, n_sectors_search=ns,
+                                      max_tracklets=m if variant == "paper" else 0)
+        res = utc.compass_find(geom, p, b.n_events, hits, *vel, vo)
+        for _ in range(args.warmup):
+            utc.compass_find(geom, p, b.n_events, hits, *vel, vo, out=res)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            utc.compass_find(geom, p, b.n_events, hits, *vel, vo, out=res)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        eff = efficiency(b, res["hit_idx"].cpu().numpy(), res["nhits"].cpu().numpy())
+        print(json.dumps({"workload": args.workload, "search": variant, "sectors": ns, "candidates": m,
+                          "compass_find_ms": round(ms, 5),
+                          "events_per_s": round(b.n_events / (ms * 1e-3), 1),
+                          **{k: round(v, 5) if isinstance(v, float) else v for k, v in eff.items()}}),
+              flush=True)
 
 
 def copy_calibration():

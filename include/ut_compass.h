@@ -68,6 +68,11 @@ typedef struct {
   int32_t n_sectors_search;  /* 1, 3 or 5 */
   float slope_tol;           /* anchor pair accepted if |t_pair - tx_velo| <= slope_tol */
   float completion_tol;      /* completion interval margin (mm) */
+  int32_t max_tracklets;     /* 0: minimum over every compatible combination; N > 0: the search of
+                                Section V-B as the paper runs it: per anchor pair the compatible
+                                hit closest to the pair-slope extrapolation in each completion
+                                layer (first on a tie), anchor pairs in window order, stop after
+                                N tracklets */
 } utc_compass_params;
 
 /* Launch shape.  NULL selects the defaults.  block: threads per workgroup (64..1024, multiple of

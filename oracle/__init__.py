@@ -37,7 +37,8 @@ class OraDetector(ctypes.Structure):
 
 class OraParams(ctypes.Structure):
     _fields_ = [("w0", _f), ("kw", _f), ("p_min", _f), ("max_hits", ctypes.c_int32),
-                ("n_sectors_search", ctypes.c_int32), ("slope_tol", _f), ("completion_tol", _f)]
+                ("n_sectors_search", ctypes.c_int32), ("slope_tol", _f), ("completion_tol", _f),
+                ("max_tracklets", ctypes.c_int32)]
 
 
 def build(force: bool = False) -> str:
@@ -98,6 +99,7 @@ def make_params_struct(p):
     s.w0, s.kw, s.p_min = float(p.w0), float(p.kw), float(p.p_min)
     s.max_hits, s.n_sectors_search = int(p.max_hits), int(p.n_sectors_search)
     s.slope_tol, s.completion_tol = float(p.slope_tol), float(p.completion_tol)
+    s.max_tracklets = int(getattr(p, "max_tracklets", 0))
     return s
 
 

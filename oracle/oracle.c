@@ -252,6 +252,7 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
 
       for (int dir = 0; dir < 2 && !best.valid; ++dir) {
         const int A = DIRS[dir][0], B = DIRS[dir][1], C[2] = {DIRS[dir][2], DIRS[dir][3]};
+        int n_tracklets = 0;
         const float inv_dz_ab = 1.0f / (det->z_layer[B] - det->z_layer[A]);
         for (int64_t iA = wf[A]; iA < we[A]; ++iA) {
           /* the strip must cover the track's y (the VELO tolerance check of Section V-A) */
@@ -279,6 +280,38 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
                 if (lo <= m && m <= hi) compat[k][ncompat[k]++] = (int32_t)i;
               }
             }
+            if (par->max_tracklets > 0) {
+              /* the paper's search (Section V-B): in each completion panel the compatible hit
+                 closest to the pair-slope extrapolation (the first one on a tie); the pair makes a
+                 tracklet when at least one is found; the search stops after max_tracklets tracklets */
+              int32_t best_hit[2] = {-1, -1};
+              for (int k = 0; k < 2; ++k) {
+                float d = det->z_layer[C[k]] - det->z_layer[A];
+                float xt = mA + slope * d;
+                float bd = 0.0f;
+                for (int q = 0; q < ncompat[k]; ++q) {
+                  int32_t i = compat[k][q];
+                  float m = hit_u[i] + x.yl[C[k]] * det->dxdy[C[k]];
+                  float dist = fabsf(m - xt);
+                  if (best_hit[k] < 0 || dist < bd) { best_hit[k] = i; bd = dist; }
+                }
+              }
+              if (best_hit[0] < 0 && best_hit[1] < 0) continue;
+              int32_t idx[NL];
+              idx[A] = (int32_t)iA;
+              idx[B] = (int32_t)iB;
+              idx[C[0]] = best_hit[0];
+              idx[C[1]] = best_hit[1];
+              int n = 2 + (best_hit[0] >= 0) + (best_hit[1] >= 0);
+              float q, c2;
+              fit_candidate(det, &x, hit_u, hit_weight, idx, &q, &c2);
+              if (better(n, c2, idx, &best)) {
+                best.valid = 1; best.nhits = n; best.qop = q; best.chi2 = c2;
+                memcpy(best.idx, idx, sizeof idx);
+              }
+              if (++n_tracklets >= par->max_tracklets) goto direction_done;
+              continue;
+            }
             /* every candidate: both anchors, each completion panel with one compatible hit or
                none, at least three hits */
             for (int k1 = -1; k1 < ncompat[0]; ++k1) {
@@ -300,6 +333,7 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
             }
           }
         }
+      direction_done:;
         /* the backward direction is only tried when the forward one found nothing */
       }
       if (best.valid) {

@@ -57,6 +57,8 @@ typedef struct {
   int32_t n_sectors_search;    /* 1, 3 or 5 */
   float slope_tol;             /* |t_pair - tx| bound */
   float completion_tol;        /* completion interval margin (mm) */
+  int32_t max_tracklets;       /* 0: every compatible combination; N > 0: the paper's search with
+                                  the closest completion hit per layer, stopping after N tracklets */
 } ora_params;
 
 /* Decode: banks b = (e*4 + l)*S + s hold words[bank_offsets[b] .. bank_offsets[b+1]).

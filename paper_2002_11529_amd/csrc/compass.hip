@@ -10,6 +10,9 @@
 
 namespace utc {
 
+// kGreedy: the paper's search variant (max_tracklets > 0), a kernel of its own so that its code
+// does not weigh on the register allocation of the default search
+template <bool kGreedy>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
           const float* __restrict__ hu, const float* __restrict__ hw,
@@ -87,13 +90,13 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     if (staged) {
       for (uint32_t grp = wid; grp < ngroups; grp += nwaves) {
         const LaneState next = load_state(io, t0 + (grp + nwaves) * kGroupTracks, t1);
-        compass_group<true, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
+        compass_group<true, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
         st = next;
       }
     } else {
       for (uint32_t grp = wid; grp < ngroups; grp += nwaves) {
         const LaneState next = load_state(io, t0 + (grp + nwaves) * kGroupTracks, t1);
-        compass_group<false, false>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
+        compass_group<false, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
         st = next;
       }
     }
@@ -130,6 +133,7 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   if (!geom || !params || geom->n_layers != kLayers || geom->n_sectors < 1 ||
       geom->n_sectors > 8192 || n_events < 0 || n_tracks < 0 || n_tracks > INT32_MAX)
     return UTC_ERR_ARG;
+  if (params->max_tracklets < 0) return UTC_ERR_ARG;
   if (params->max_hits < 1 || params->max_hits > UTC_MAX_WINDOW_HITS ||
       params->n_sectors_search < 1 || params->n_sectors_search % 2 == 0)
     return UTC_ERR_ARG;
@@ -149,6 +153,7 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   p.half = (params->n_sectors_search - 1) / 2;
   p.slope_tol = params->slope_tol;
   p.eps = params->completion_tol;
+  p.max_tracklets = params->max_tracklets;
   // the pruning bound needs positive kick factors
   p.prune = 1;
   for (int l = 0; l < kLayers; ++l)
@@ -166,9 +171,16 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   (void)hipGetLastError();  // report only errors of this call
   const int grid = (launch && launch->grid > 0) ? launch->grid : n_events;
   TrackIO io{vx, vy, vtx, vty, hit_idx, qop, chi2, nhits, windows};
-  if (!allow_dynamic_lds(reinterpret_cast<const void*>(k_compass), lds)) return UTC_ERR_HIP;
-  hipLaunchKernelGGL(k_compass, dim3(grid), dim3(block), lds, stream, g, p, n_events, hit_offsets,
-                     hit_u, hit_weight, hit_y_begin, hit_y_end, velo_offsets, io, error_flags,
-                     u_cap);
+  const void* kern = p.max_tracklets > 0 ? reinterpret_cast<const void*>(k_compass<true>)
+                                          : reinterpret_cast<const void*>(k_compass<false>);
+  if (!allow_dynamic_lds(kern, lds)) return UTC_ERR_HIP;
+  if (p.max_tracklets > 0)
+    hipLaunchKernelGGL(k_compass<true>, dim3(grid), dim3(block), lds, stream, g, p, n_events,
+                       hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end, velo_offsets, io,
+                       error_flags, u_cap);
+  else
+    hipLaunchKernelGGL(k_compass<false>, dim3(grid), dim3(block), lds, stream, g, p, n_events,
+                       hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end, velo_offsets, io,
+                       error_flags, u_cap);
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
 }

@@ -26,6 +26,7 @@ struct CPar {
   float slope_tol;
   float eps;          // completion interval margin (mm)
   int prune;          // lower-bound pruning of 4-hit candidates allowed (kick factors > 0)
+  int max_tracklets;  // 0: every compatible combination; N > 0: the paper's search, N tracklets
 };
 
 // Hits of the current event as seen by the search.  kULds / kWLds: u / weight read from LDS
@@ -337,6 +338,22 @@ __device__ inline uint32_t nearest_slot(const Geom& g, const GroupScratch& s, in
   return arg;
 }
 
+// The slot of mask m in layer Cl whose x is closest to the pair-slope extrapolation from the first
+// anchor (the first one on a tie), as a one-bit mask; 0 for an empty mask.
+__device__ inline uint32_t closest_slot_mask(const Geom& g, const GroupScratch& s, int t, int A, int Cl,
+                                             uint32_t m, float mA, float slope) {
+  const float xt = mA + slope * (g.z_layer[Cl] - g.z_layer[A]);
+  uint32_t arg = 0u;
+  float bd = 0.0f;
+  bool any = false;
+  for (uint32_t mm = m; mm; mm &= mm - 1) {
+    const uint32_t j = (uint32_t)__builtin_ctz(mm);
+    const float dist = fabsf(s.tm[tile_at(t, Cl, (int)j)] - xt);
+    if (!any || dist < bd) { arg = j; bd = dist; any = true; }
+  }
+  return any ? (1u << arg) : 0u;
+}
+
 // One batch of at most 64 passing anchor pairs (s.bp, pairs of one track contiguous): completion
 // masks, for 4-hit candidates the seed and the pruning, then the candidates flattened over the
 // lanes; each candidate's key is folded into its track's minimum.
@@ -356,6 +373,30 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     completion_ranges(g, p, s, tt, A, C1, C2, mA, slope, m1, m2);
     m1 &= s.umask[tt * 4 + C1];
     m2 &= s.umask[tt * 4 + C2];
+  }
+  if (nhits == 0) {
+    // the paper's search: per pair the completion hit closest to the pair-slope extrapolation in
+    // each layer (first on a tie); a pair with at least one is a tracklet; only the first
+    // max_tracklets tracklets of each track, in pair order, are candidates
+    bool is_tl = false;
+    if ((uint32_t)lane < np) {
+      const float mA = s.tm[tile_at(tt, A, jA)];
+      const float slope = (s.tm[tile_at(tt, B, jB)] - mA) * inv_dz_ab;
+      m1 = closest_slot_mask(g, s, tt, A, C1, m1, mA, slope);
+      m2 = closest_slot_mask(g, s, tt, A, C2, m2, mA, slope);
+      is_tl = (m1 | m2) != 0u;
+    }
+    // rank of this tracklet among its track's tracklets of the batch (pairs of a track are
+    // contiguous lanes), plus the track's tracklets of earlier batches
+    const uint64_t tl = ballot(is_tl);
+    const int prev_tt = __shfl_up(tt, 1, kWave);
+    const bool start = (uint32_t)lane < np && (lane == 0 || prev_tt != tt);
+    const uint32_t first = wave_inclusive_max(start ? (uint32_t)lane : 0u);
+    const uint32_t rank = (uint32_t)__popcll(tl & __lanemask_lt() & ~((1ull << first) - 1ull));
+    const bool take = is_tl && (uint32_t)s.lbk[tt] + rank < (uint32_t)p.max_tracklets;
+    wave_sync();
+    if (is_tl) atomicAdd(&s.lbk[tt], 1ull);
+    if (!take) { m1 = 0u; m2 = 0u; }
   }
   // pruning pays for itself only when the batch has many 4-hit candidates
   uint32_t full_tot = 0;
@@ -406,7 +447,7 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     s.bm1[lane] = m1;
     s.bm2[lane] = m2;
     const uint32_t n1 = (uint32_t)__popc(m1), n2 = (uint32_t)__popc(m2);
-    ncand = nhits == 4 ? n1 * n2 : n1 + n2;
+    ncand = nhits == 4 ? n1 * n2 : (nhits == 3 ? n1 + n2 : ((m1 | m2) ? 1u : 0u));
   }
   uint32_t ctot;
   const uint32_t coff = wave_excl_scan(ncand, &ctot);
@@ -431,7 +472,10 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
       const uint32_t rr = ci - s.boff[pi];
       const uint32_t c1m = s.bm1[pi], c2m = s.bm2[pi];
       uint32_t k1, k2;  // window slot + 1 of the completion hits, 0 = none
-      if (nhits == 4) {
+      if (nhits == 0) {
+        k1 = c1m ? (uint32_t)__builtin_ctz(c1m) + 1u : 0u;
+        k2 = c2m ? (uint32_t)__builtin_ctz(c2m) + 1u : 0u;
+      } else if (nhits == 4) {
         const uint32_t n2 = (uint32_t)__popc(c2m);
         const uint32_t i1 = rr / n2;
         k1 = nth_set_bit(c1m, i1) + 1u;
@@ -450,7 +494,8 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
         code[q] = q == A ? a1 + 1u : q == B ? b1 + 1u : q == C1 ? k1 : k2;
       float qop, chi2;
       fit_codes(g, s, t2, code, qop, chi2);
-      atomicMin(&s.best[t2], make_key(nhits, chi2, code));
+      const int nh = nhits != 0 ? nhits : 2 + (k1 != 0u) + (k2 != 0u);
+      atomicMin(&s.best[t2], make_key(nh, chi2, code));
     }
   }
   wave_sync();
@@ -467,6 +512,7 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
   int A, B, C1, C2;
   dir_layers(dir, A, B, C1, C2);
   const float inv_dz_ab = 1.0f / (g.z_layer[B] - g.z_layer[A]);
+  if (nhits == 0 && lane < kGroupTracks) s.lbk[lane] = 0ull;   // tracklets found per track
   const uint32_t cnt = (l == 0 && want_lane) ? (uint32_t)s.nwin[t * 4 + A] : 0u;
   uint32_t total;
   const uint32_t off = wave_excl_scan(cnt, &total);
@@ -517,9 +563,14 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
 
 // One direction: the 4-hit candidates first; a 3-hit candidate can never be selected over a 4-hit
 // one, so 3-hit candidates are only searched for the tracks without a 4-hit candidate.
+template <bool kGreedy>
 __device__ inline void search_direction(const Geom& g, const CPar& p, const GroupScratch& s,
                                         int dir, bool want_lane) {
   const int t = lane_id() >> 2;
+  if constexpr (kGreedy) {   // the paper's search: one pass, 3- and 4-hit tracklets together
+    run_direction(g, p, s, dir, 0, want_lane);
+    return;
+  }
   run_direction(g, p, s, dir, 4, want_lane);
   const bool need3 = want_lane && s.best[t] == kNoKey;
   if (wave_any(need3)) run_direction(g, p, s, dir, 3, need3);
@@ -559,7 +610,7 @@ __device__ inline LaneState load_state(const TrackIO& io, uint32_t tbase, uint32
   return st;
 }
 
-template <bool kULds, bool kWLds>
+template <bool kULds, bool kWLds, bool kGreedy>
 __device__ inline void compass_group(const Geom& g, const CPar& p, const EventView& ev,
                                      const GroupScratch& s, uint32_t tbase, uint32_t t1,
                                      const TrackIO& io, const LaneState& st)
@@ -689,9 +740,9 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   wave_sync();
 
   // tracklets (Section V-B): forward anchors first; backward only where forward found nothing
-  search_direction(g, p, s, 0, active);
+  search_direction<kGreedy>(g, p, s, 0, active);
   const bool need_back = active && s.best[t] == kNoKey;
-  if (wave_any(need_back)) search_direction(g, p, s, 1, need_back);
+  if (wave_any(need_back)) search_direction<kGreedy>(g, p, s, 1, need_back);
 
   const unsigned long long key = active ? s.best[t] : kNoKey;
   const bool found = key != kNoKey;

@@ -93,6 +93,8 @@ class CompassParams:
     Window half-width W = w0 + kw / p_min (mm).  max_hits is the per-layer window cap (the
     "number of hit candidates"), n_sectors_search the 1/3/5 sector choice (Section V-A).
     slope_tol bounds |t_pair - tx_velo|; completion_tol widens the completion interval (mm).
+    max_tracklets 0 selects the minimum over every compatible combination; N > 0 the paper's
+    search (closest completion hit per layer, stop after N tracklets, Section V-B).
     """
     w0: np.float32
     kw: np.float32
@@ -101,15 +103,17 @@ class CompassParams:
     n_sectors_search: int
     slope_tol: np.float32
     completion_tol: np.float32
+    max_tracklets: int = 0
 
 
 def make_compass_params(p_min_mev: float = 1500.0, max_hits: int = 8, n_sectors_search: int = 5,
                         w0_mm: float = 0.5, kw_mm_mev: float = 1500.0,
-                        completion_tol_mm: float = 0.5) -> CompassParams:
+                        completion_tol_mm: float = 0.5, max_tracklets: int = 0) -> CompassParams:
     # The pair slope differs from the VELO slope by at most the kick K/(p_min*lever), plus the
     # resolution term 2*eps over the anchor lever arm of 270 mm.
     slope_tol = K_KICK_MM_MEV / (p_min_mev * L_LEVER_MM) + 2.0 * completion_tol_mm / 270.0
     return CompassParams(
         w0=np.float32(w0_mm), kw=np.float32(kw_mm_mev), p_min=np.float32(p_min_mev),
         max_hits=int(max_hits), n_sectors_search=int(n_sectors_search),
-        slope_tol=np.float32(slope_tol), completion_tol=np.float32(completion_tol_mm))
+        slope_tol=np.float32(slope_tol), completion_tol=np.float32(completion_tol_mm),
+        max_tracklets=int(max_tracklets))

@@ -369,3 +369,49 @@ def test_layer_overflow_flag():
                        np.array([0, 1, 2], np.uint32), with_windows=True)
     assert c["flags"] & oracle.FLAG_LAYER_OVERFLOW
     assert c["active"][0] == 0 and c["active"][1] == 1
+
+
+def test_greedy_variant_properties():
+    """The paper's variant: with a budget of one tracklet the result is the first tracklet in window
+    order; a budget larger than the number of pairs gives the minimum over one candidate per pair,
+    which can never beat the exhaustive minimum."""
+    b = synth.generate("tiny", n_events=6, seed=13)
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    ex = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx, b.velo_ty,
+                        b.velo_offsets)
+    big = synth.make_compass_params(p_min_mev=float(b.params.p_min), max_hits=b.params.max_hits,
+                                    n_sectors_search=b.params.n_sectors_search, max_tracklets=1 << 20)
+    one = synth.make_compass_params(p_min_mev=float(b.params.p_min), max_hits=b.params.max_hits,
+                                    n_sectors_search=b.params.n_sectors_search, max_tracklets=1)
+    g = oracle.compass(b.detector, big, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx, b.velo_ty,
+                       b.velo_offsets)
+    g1 = oracle.compass(b.detector, one, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx, b.velo_ty,
+                        b.velo_offsets)
+    # the same tracks get a tracklet (one exists iff some passing pair has a compatible hit)
+    assert np.array_equal(g["nhits"] > 0, ex["nhits"] > 0)
+    assert np.array_equal(g1["nhits"] > 0, ex["nhits"] > 0)
+    both = (ex["nhits"] == 4) & (g["nhits"] == 4)
+    assert both.sum() > 0
+    # the exhaustive minimum is never worse; where the greedy choice is a 4-hit one it is one of
+    # the exhaustive candidates, so its chi2 is at least the exhaustive 4-hit minimum
+    assert np.all(ex["chi2"][both] <= g["chi2"][both])
+    assert np.all(ex["nhits"] >= g["nhits"])
+    # a budget of one tracklet can never select better than a larger budget
+    sel = (g1["nhits"] == g["nhits"]) & (g["nhits"] > 0)
+    assert np.all(g["chi2"][sel] <= g1["chi2"][sel])
+    assert np.all(np.isfinite(g["chi2"][g["nhits"] > 0]))
+
+
+def test_greedy_variant_equals_exhaustive_for_single_hit_windows():
+    """With one hit per window every pair has at most one compatible hit per completion layer, so
+    the closest-hit choice and the exhaustive minimum coincide (budget above the pair count)."""
+    b = synth.generate("realistic", n_events=8, seed=14)
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    kw = dict(p_min_mev=float(b.params.p_min), max_hits=1, n_sectors_search=5)
+    ex = oracle.compass(b.detector, synth.make_compass_params(**kw), b.n_events, d, b.velo_x, b.velo_y,
+                        b.velo_tx, b.velo_ty, b.velo_offsets)
+    g = oracle.compass(b.detector, synth.make_compass_params(**kw, max_tracklets=1000), b.n_events, d,
+                       b.velo_x, b.velo_y, b.velo_tx, b.velo_ty, b.velo_offsets)
+    assert (ex["nhits"] == 4).sum() > 0
+    for k in ("nhits", "hit_idx", "qop", "chi2"):
+        assert np.array_equal(ex[k], g[k]), k
