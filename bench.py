@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="skip the step timed on the compact hit form (no per-hit z / y range)")
     ap.add_argument("--no-fitgrad", action="store_true",
                     help="skip the fit-chi2 forward/backward figure on the 1e6-track workload")
     ap.add_argument("--sweep", action="store_true",
@@ -97,8 +99,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so "
-              "the path shards by event ranges with no exchange; multi-GPU runs are not part of "
-              "this build.", file=sys.stderr)
+              "the path shards by event ranges with no exchange; multi-GPU runs are not "
+              "supported.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -157,20 +159,23 @@ def main():
     lau_dec = tuned["decode"] if tuned else None
     lau_find = tuned["find"] if tuned else None
 
-    def step(c, ev=None):
+    def step(c, ev=None, compact=False):
         stream = torch.cuda.current_stream()
+        # the compact form passes no z / y_begin / y_end: the decoder skips those stores and the
+        # search takes the detector's y range for every strip
+        hits = {k: c["hits"][k] for k in ("hit_offsets", "lhcbid", "u", "weight")} if compact else c["hits"]
         if ev is not None:
             ev[0].record(stream)
         utc.ut_decode(geom, c["words"], c["boff"], E, hit_capacity=b.n_words, error_flags=flags,
-                      out=c["hits"], workspace=ws_dec, launch=lau_dec)
+                      out=hits, workspace=ws_dec, launch=lau_dec)
         if ev is not None:
             ev[1].record(stream)
-        utc.compass_find(geom, params, E, c["hits"], *c["vel"], c["vo"], error_flags=flags,
+        utc.compass_find(geom, params, E, hits, *c["vel"], c["vo"], error_flags=flags,
                          out=c["res"], workspace=ws_find, launch=lau_find)
         if ev is not None:
             ev[2].record(stream)
-        utc.compass_fit_grad(geom, c["res"]["hit_idx"], c["hits"]["u"], c["hits"]["weight"],
-                             c["hits"]["lhcbid"], *c["vel"], c["res"]["qop"], offsets,
+        utc.compass_fit_grad(geom, c["res"]["hit_idx"], hits["u"], hits["weight"],
+                             hits["lhcbid"], *c["vel"], c["res"]["qop"], offsets,
                              out=c["fg"], workspace=ws_fg)
         if ev is not None:
             ev[3].record(stream)
@@ -229,6 +234,38 @@ def main():
     ms_per_step = ms_total / K
     if int(flags.item()) != 0:
         raise RuntimeError(f"device error flags {int(flags.item())}")
+
+    # the same step on the compact hit form, timed the same way
+    compact = None
+    if not args.no_compact:
+        gc = None
+        if graphs is not None:
+            gc = []
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                for c in copies:
+                    gph = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(gph, stream=side):
+                        step(c, compact=True)
+                    gc.append(gph)
+            torch.cuda.current_stream().wait_stream(side)
+        run = (lambda i: gc[i % R].replay()) if gc is not None else (lambda i: step(copies[i % R], compact=True))
+        for i in range(args.warmup):
+            run(i)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for i in range(K):
+            run(i)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        if int(flags.item()) != 0:
+            raise RuntimeError(f"device error flags {int(flags.item())}")
+        cms = c0.elapsed_time(c1) / K
+        compact = {"events_per_s": round(E / (cms * 1e-3), 1), "ms_per_step": round(cms, 5),
+                   "what": "the same step with the decoder writing lhcbid/u/weight only (12 B per hit) "
+                           "and the search taking the detector's y range for every strip"}
 
     # the same decode + Compass work launched one event at a time (eager), for comparison
     per_event = None
@@ -290,6 +327,7 @@ def main():
         "timing": "hip graph replay" if graphs is not None else "eager launches",
         "launch": {"decode": lau_dec, "find": lau_find, "source": "autotuner" if tuned else "defaults"},
         "batched_vs_per_event": per_event,
+        "compact_hits": compact,
         "found_fraction": round(n_found / max(Nt, 1), 5),
         "wall_s": round(wall, 4),
     }

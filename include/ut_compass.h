@@ -98,7 +98,9 @@ typedef struct {
  *   u = fmaf(8*strip + fraction, pitch8, u0[l*S + s]) (x at y = 0);  y_begin, y_end;
  *   weight = weight_by_size[size].
  * The six output arrays must hold hit_capacity elements; hits past it are not stored
- * (UTC_FLAG_CAPACITY).  Pass hit_capacity >= number of words to be safe.
+ * (UTC_FLAG_CAPACITY).  Pass hit_capacity >= number of words to be safe.  z, y_begin and y_end
+ * are layer / geometry constants and may be NULL (not written): the compact form of the hit
+ * structure, 12 instead of 24 bytes per hit.
  * Workspace: ut_decode_workspace_bytes(n_events, S) bytes of device memory, any content.
  * --------------------------------------------------------------------------------------------- */
 size_t ut_decode_workspace_bytes(int32_t n_events, int32_t n_sectors);
@@ -120,6 +122,8 @@ utc_status ut_decode(const utc_geometry* geom, const uint16_t* words, const uint
  * nhits (0 = no upstream track, else 3 or 4), qop (MeV^-1, its sign is the charge) and chi2 of the
  * fit; zeros for tracks without a tracklet.  windows (optional, NULL to skip): int16 pairs
  * [4t + l] = (first hit - first hit of its (event, layer), size), (-1, 0) when not searched.
+ * hit_y_begin and hit_y_end may both be NULL: every strip then spans the geometry's
+ * [y_begin, y_end] (what ut_decode writes; the compact form of the hits).
  * Workspace: compass_find_workspace_bytes() bytes, any content.
  * --------------------------------------------------------------------------------------------- */
 size_t compass_find_workspace_bytes(int32_t n_events, int64_t n_tracks);

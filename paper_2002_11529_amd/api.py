@@ -165,8 +165,9 @@ def _workspace(nbytes, device):
 
 
 def ut_decode(geom: Geometry, words, bank_offsets, n_events: int, hit_capacity: Optional[int] = None,
-              error_flags=None, launch=None, out=None, workspace=None, stream=None):
-    """Decode raw banks into the hit structure of arrays.  Returns a dict of device tensors."""
+              error_flags=None, launch=None, out=None, workspace=None, stream=None, compact=False):
+    """Decode raw banks into the hit structure of arrays.  Returns a dict of device tensors.
+    compact=True leaves out the layer / geometry constants z, y_begin and y_end."""
     L = library()
     dev = words.device
     n_banks = n_events * 4 * geom.n_sectors
@@ -176,19 +177,19 @@ def ut_decode(geom: Geometry, words, bank_offsets, n_events: int, hit_capacity: 
     if out is None:
         out = dict(hit_offsets=torch.empty(n_banks + 1, dtype=torch.int32, device=dev),
                    lhcbid=torch.empty(cap, dtype=torch.int32, device=dev),
-                   z=torch.empty(cap, dtype=torch.float32, device=dev),
                    u=torch.empty(cap, dtype=torch.float32, device=dev),
-                   y_begin=torch.empty(cap, dtype=torch.float32, device=dev),
-                   y_end=torch.empty(cap, dtype=torch.float32, device=dev),
                    weight=torch.empty(cap, dtype=torch.float32, device=dev))
+        if not compact:
+            for k in ("z", "y_begin", "y_end"):
+                out[k] = torch.empty(cap, dtype=torch.float32, device=dev)
     if error_flags is None:
         error_flags = torch.zeros(1, dtype=torch.int32, device=dev)
     out["error_flags"] = error_flags
     if workspace is None:
         workspace = _workspace(L.ut_decode_workspace_bytes(n_events, geom.n_sectors), dev)
     st = L.ut_decode(geom.ref, _ptr(words), _ptr(bank_offsets), n_events, cap,
-                     _ptr(out["hit_offsets"]), _ptr(out["lhcbid"]), _ptr(out["z"]), _ptr(out["u"]),
-                     _ptr(out["y_begin"]), _ptr(out["y_end"]), _ptr(out["weight"]),
+                     _ptr(out["hit_offsets"]), _ptr(out["lhcbid"]), _ptr(out.get("z")), _ptr(out["u"]),
+                     _ptr(out.get("y_begin")), _ptr(out.get("y_end")), _ptr(out["weight"]),
                      _ptr(error_flags), _ptr(workspace), workspace.numel(), _launch(launch),
                      _stream(stream))
     _check(st, "ut_decode")
@@ -218,8 +219,8 @@ def compass_find(geom: Geometry, params, n_events: int, hits, vx, vy, vtx, vty, 
         workspace = _workspace(L.compass_find_workspace_bytes(n_events, n), dev)
     p = params if isinstance(params, UtcCompassParams) else compass_params(params)
     st = L.compass_find(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"]),
-                        _ptr(hits["u"]), _ptr(hits["weight"]), _ptr(hits["y_begin"]),
-                        _ptr(hits["y_end"]), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty),
+                        _ptr(hits["u"]), _ptr(hits["weight"]), _ptr(hits.get("y_begin")),
+                        _ptr(hits.get("y_end")), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty),
                         _ptr(velo_offsets), n, _ptr(out["hit_idx"]), _ptr(out["qop"]),
                         _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out.get("windows")),
                         _ptr(error_flags), _ptr(workspace), workspace.numel(), _launch(launch),

@@ -138,9 +138,10 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
       params->n_sectors_search < 1 || params->n_sectors_search % 2 == 0)
     return UTC_ERR_ARG;
   if (n_events > 0 && (!hit_offsets || !velo_offsets)) return UTC_ERR_ARG;
-  if (n_tracks > 0 && (!hit_u || !hit_weight || !hit_y_begin || !hit_y_end || !vx || !vy || !vtx ||
-                       !vty || !hit_idx || !qop || !chi2 || !nhits))
+  if (n_tracks > 0 && (!hit_u || !hit_weight || !vx || !vy || !vtx || !vty || !hit_idx || !qop ||
+                       !chi2 || !nhits))
     return UTC_ERR_ARG;
+  if ((hit_y_begin == nullptr) != (hit_y_end == nullptr)) return UTC_ERR_ARG;
   if (launch && (launch->block < 64 || launch->block > 256 || launch->block % 64 || launch->grid < 0))
     return UTC_ERR_ARG;
   if (!workspace || workspace_bytes < compass_find_workspace_bytes(n_events, n_tracks))

@@ -104,7 +104,7 @@ extern "C" utc_status ut_decode(const utc_geometry* geom, const uint16_t* words,
   if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
       !geom->u0 || n_events < 0 || hit_capacity < 0 || !bank_offsets || !hit_offsets)
     return UTC_ERR_ARG;
-  if (n_events > 0 && hit_capacity > 0 && (!words || !lhcbid || !z || !u || !y_begin || !y_end || !weight))
+  if (n_events > 0 && hit_capacity > 0 && (!words || !lhcbid || !u || !weight))
     return UTC_ERR_ARG;
   if (launch && (launch->block < 64 || launch->block > 1024 || launch->block % 64 || launch->grid < 0))
     return UTC_ERR_ARG;

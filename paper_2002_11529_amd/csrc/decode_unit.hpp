@@ -184,10 +184,10 @@ __device__ inline void store_hit(const Geom& g, int layer, const DecodedHit& d, 
     return;
   }
   out.lhcbid[h] = d.lhcbid;
-  out.z[h] = g.z_layer[layer];
+  if (out.z) out.z[h] = g.z_layer[layer];   // the layer constants are optional outputs
   out.u[h] = d.u;
-  out.y_begin[h] = g.y_begin;
-  out.y_end[h] = g.y_end;
+  if (out.y_begin) out.y_begin[h] = g.y_begin;
+  if (out.y_end) out.y_end[h] = g.y_end;
   out.weight[h] = d.w;
 }
 
