@@ -299,6 +299,7 @@ def main():
     dom = int(np.argmax(call_ms))
     achieved = per_call_bytes[dom] / (call_ms[dom] * 1e-3) / 1e9
     value = E / (ms_per_step * 1e-3)
+    copy_bw = copy_bandwidth()
 
     out = {
         "metric": "events/s UT decode+Compass @1 GPU (HBM GB/s); fwd+bwd fitted tracks/s",
@@ -320,7 +321,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload)},
+                     "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload),
+                     "copy_GBps": round(copy_bw, 1), "frac_of_copy": round(achieved / copy_bw, 4)},
         "calls_ms": {n: round(float(m), 5) for n, m in zip(names, call_ms)},
         "step_algorithmic_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "decode_GBps": round(bytes_decode / (call_ms[0] * 1e-3) / 1e9, 1),
@@ -438,6 +440,28 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_read": n, "bytes_written": n, "copies": 5}), flush=True)
 
 
+def copy_bandwidth(reps=10):
+    """Measured streaming bandwidth of the card: a 1 GiB device-to-device copy (read + write bytes
+    per second), median of `reps` copies timed with HIP events."""
+    import numpy as np
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n / (float(np.median(ms)) * 1e-3) / 1e9
+
+
 def bench_fitgrad(args, dev):
     """Fit-chi2 forward + backward over the frozen tracks of the differentiation workload (21000
     events, about 1.05e6 tracks with 3 or 4 hits), against the same calls launched per event."""
@@ -544,10 +568,36 @@ def cpu_baseline(b, seconds):
         one_pass(sub)
         reps += 1
         t = time.perf_counter() - t0
-    return {"value": round(reps * sub.n_events / t, 1), "unit": "events/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{reps} passes over the first {sub.n_events} of the {b.n_events} events "
-                      f"(decode + Compass + fit-chi2 fwd+bwd), single thread, {t:.1f} s"}
+    out = {"value": round(reps * sub.n_events / t, 1), "unit": "events/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{reps} passes over the first {sub.n_events} of the {b.n_events} events "
+                     f"(decode + Compass + fit-chi2 fwd+bwd), single thread, {t:.1f} s"}
+
+    # the same oracle on every host core given to this process: events are independent, so the
+    # sample is split into one slice per thread (the oracle's C calls release the interpreter lock)
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0)), sub.n_events))
+    cuts = np.linspace(0, sub.n_events, cores + 1).astype(np.int64)
+    slices = [synth.take_events(sub, np.arange(cuts[i], cuts[i + 1])) for i in range(cores)]
+    budget = seconds / 2
+
+    def worker(sl):
+        n, t1 = 0, time.perf_counter()
+        while True:
+            one_pass(sl)
+            n += sl.n_events
+            if time.perf_counter() - t1 >= budget:
+                return n
+
+    t1 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        done = sum(ex.map(worker, slices))
+    t = time.perf_counter() - t1
+    out["all_cores"] = {"value": round(done / t, 1), "unit": "events/s", "cores": cores,
+                        "sample": f"the same {sub.n_events} events split over {cores} threads, each "
+                                  f"repeating its slice for {budget:.0f} s ({t:.1f} s wall)"}
+    return out
 
 
 if __name__ == "__main__":

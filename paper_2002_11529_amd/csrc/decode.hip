@@ -66,18 +66,16 @@ k_decode_scan(const uint32_t* __restrict__ unit_sum, int n_units, uint32_t* __re
 
 __global__ void __launch_bounds__(1024)
 k_decode(Geom g, const uint16_t* __restrict__ words, const uint32_t* __restrict__ bank_offsets,
-         int n_units, int64_t capacity, const uint32_t* __restrict__ unit_base,
+         int n_units, int cap, int64_t capacity, const uint32_t* __restrict__ unit_base,
          uint32_t* __restrict__ hit_offsets, HitsOut out, uint32_t* flags)
 {
   extern __shared__ __align__(16) char smem[];
   const int wid = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
-  const WaveScratch ws = carve_scratch(smem + (size_t)wid * wave_scratch_bytes(g.S), g.S);
+  const WaveScratch ws = carve_scratch(smem + (size_t)wid * wave_scratch_bytes(g.S, cap), g.S, cap);
   for (int u = blockIdx.x * nwaves + wid; u < n_units; u += gridDim.x * nwaves) {
     const int64_t b0 = (int64_t)u * g.S;
-    const UnitCount st = unit_count(g, words, bank_offsets, b0, ws, flags);
-    stage_tables(g, u % kLayers, ws);
-    unit_write(g, words, u % kLayers, b0, unit_base[u], st, ws, capacity, hit_offsets, out, flags,
-               nullptr, nullptr, 0);
+    const UnitCount st = unit_count(g, words, bank_offsets, b0, ws, flags, u % kLayers);
+    unit_write(g, words, u % kLayers, b0, unit_base[u], st, ws, capacity, hit_offsets, out, flags);
     wave_sync();
   }
 }
@@ -116,11 +114,12 @@ extern "C" utc_status ut_decode(const utc_geometry* geom, const uint16_t* words,
   uint32_t* unit_sum = static_cast<uint32_t*>(workspace);
   uint32_t* unit_base = unit_sum + n_units;
   const Geom g = make_geom(*geom);
+  const int cap = chunk_words(S);
   int block = launch ? launch->block : 256;
-  while (!launch && block > kWave && (size_t)(block / kWave) * wave_scratch_bytes(S) > 160 * 1024)
+  while (!launch && block > kWave && (size_t)(block / kWave) * wave_scratch_bytes(S, cap) > 160 * 1024)
     block -= kWave;
   const int waves = block / kWave;
-  const size_t lds = (size_t)waves * wave_scratch_bytes(S);
+  const size_t lds = (size_t)waves * wave_scratch_bytes(S, cap);
   if (lds > 160 * 1024) return UTC_ERR_ARG;
   (void)hipGetLastError();  // report only errors of this call
   int grid = (launch && launch->grid > 0) ? launch->grid : (n_units + waves - 1) / waves;
@@ -143,7 +142,7 @@ extern "C" utc_status ut_decode(const utc_geometry* geom, const uint16_t* words,
   if (n_units > 0) {
     HitsOut out{lhcbid, z, u, y_begin, y_end, weight};
     hipLaunchKernelGGL(k_decode, dim3(grid), dim3(block), lds, stream, g, words, bank_offsets,
-                       n_units, hit_capacity, unit_base, hit_offsets, out, error_flags);
+                       n_units, cap, hit_capacity, unit_base, hit_offsets, out, error_flags);
   }
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
 }

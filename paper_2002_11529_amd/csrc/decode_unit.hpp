@@ -1,5 +1,5 @@
-// Decoding of one (event, layer) unit by one wavefront: the device code shared by the stand-alone
-// decoder and the fused decode + Compass kernel.
+// Decoding of one (event, layer) unit by one wavefront: the device code of the counting and the
+// decoding kernels.
 #pragma once
 
 #include "common.hpp"
@@ -7,7 +7,8 @@
 namespace utc {
 
 constexpr uint32_t kMaxBankWords = UTC_MAX_BANK_WORDS;
-constexpr int kCap = 768;            // raw words staged in LDS per chunk and wavefront
+constexpr int kMinCap = 256;         // smallest chunk of raw words staged in LDS per wavefront
+constexpr size_t kWaveLdsTarget = 10 * 1024;   // LDS per wavefront that keeps 16 waves per CU
 
 struct HitsOut {
   uint32_t* lhcbid;
@@ -18,34 +19,47 @@ struct HitsOut {
   float* weight;
 };
 
-// Per-wavefront LDS scratch.
+// Per-wavefront LDS scratch; cap = raw words staged per chunk.
 struct WaveScratch {
   uint32_t* off;    // [S+1] raw word offsets of the unit's banks
   uint32_t* hb;     // [S+1] first hit of each bank inside the current chunk
-  uint16_t* raw;    // [kCap] staged raw words
-  uint32_t* key;    // [kCap] valid words in bank order as (word << 16) | index: the sort key
-  uint16_t* cbank;  // [kCap] bank of each valid word in bank order
-  uint16_t* mark;   // [kCap] bank start markers by raw position, then valid words before it
   float* u0;        // [S] bin-0 position of each sector of the unit's layer
   float* wt;        // [16] weight of each cluster size
+  uint16_t* raw;    // [cap] staged raw words
+  uint32_t* key;
+  uint16_t* cbank;  // [cap] bank of each valid word in bank order
+  uint16_t* mark;   // [cap] bank start markers by raw position, then valid words before it
+  int cap;
 };
 
-__host__ __device__ inline size_t wave_scratch_bytes(int S) {
-  const size_t b = 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(uint32_t) * (size_t)kCap +
-                   3 * sizeof(uint16_t) * (size_t)kCap + sizeof(float) * ((size_t)S + 16);
+__host__ __device__ inline size_t wave_table_bytes(int S) {
+  return 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(float) * ((size_t)S + 16);
+}
+
+__host__ __device__ inline size_t wave_scratch_bytes(int S, int cap) {
+  const size_t b = wave_table_bytes(S) + 5 * sizeof(uint16_t) * (size_t)cap;
   return (b + 15) / 16 * 16;
 }
 
-__device__ inline WaveScratch carve_scratch(char* p, int S) {
+// Largest chunk (a multiple of 64 words, at least kMinCap) whose scratch fits kWaveLdsTarget.
+inline int chunk_words(int S) {
+  const size_t t = wave_table_bytes(S) + 16;
+  int cap = t < kWaveLdsTarget ? (int)((kWaveLdsTarget - t) / (5 * sizeof(uint16_t))) : 0;
+  cap = cap / 64 * 64;
+  return cap < kMinCap ? kMinCap : (cap > (int)kMaxBankWords ? (int)kMaxBankWords : cap);
+}
+
+__device__ inline WaveScratch carve_scratch(char* p, int S, int cap) {
   WaveScratch w;
   w.off = reinterpret_cast<uint32_t*>(p);
   w.hb = w.off + (S + 1);
-  w.key = w.hb + (S + 1);
-  w.raw = reinterpret_cast<uint16_t*>(w.key + kCap);
-  w.cbank = w.raw + kCap;
-  w.mark = w.cbank + kCap;
-  w.u0 = reinterpret_cast<float*>(w.mark + kCap);
+  w.u0 = reinterpret_cast<float*>(w.hb + (S + 1));
   w.wt = w.u0 + S;
+  w.key = reinterpret_cast<uint32_t*>(w.wt + 16);
+  w.raw = reinterpret_cast<uint16_t*>(w.key + cap);
+  w.cbank = w.raw + cap;
+  w.mark = w.cbank + cap;
+  w.cap = cap;
   return w;
 }
 
@@ -59,26 +73,33 @@ struct UnitCount {
 
 // Offsets of the unit's banks to LDS, well-formedness checks, hit count; the words are staged in
 // LDS on the way when they fit.  Uniform across the wavefront.  With ws.raw == nullptr nothing is
-// staged (count only).
+// staged (count only).  With `layer` >= 0 the layer's sector positions and the weight table are
+// staged too, their loads issued together with those of the offsets.
 __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict__ words,
                                        const uint32_t* __restrict__ bank_offsets, int64_t b0,
-                                       const WaveScratch& ws, uint32_t* flags)
+                                       const WaveScratch& ws, uint32_t* flags, int layer = -1)
 {
   const int S = g.S;
   const int lane = lane_id();
+  const float* __restrict__ u0_row = layer >= 0 ? g.u0 + (size_t)layer * S : nullptr;
+  const float wt = (u0_row && lane < 16) ? g.weight_by_size[lane] : 0.f;
   for (int s0 = 0; s0 <= S; s0 += 4 * kWave) {
     uint32_t v[4];
+    float t[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int s = s0 + k * kWave + lane;
       v[k] = s <= S ? bank_offsets[b0 + s] : 0u;
+      t[k] = (u0_row && s < S) ? u0_row[s] : 0.f;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int s = s0 + k * kWave + lane;
       if (s <= S) ws.off[s] = v[k];
+      if (u0_row && s < S) ws.u0[s] = t[k];
     }
   }
+  if (u0_row && lane < 16) ws.wt[lane] = wt;
   wave_sync();
   bool bad = false;
   for (int s = lane; s < S; s += kWave) {
@@ -98,7 +119,7 @@ __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict
   if (!st.bad) {
     const uint32_t w0 = ws.off[0];
     const uint32_t nw = ws.off[S] - w0;
-    st.staged = ws.raw != nullptr && nw <= (uint32_t)kCap;
+    st.staged = ws.raw != nullptr && nw <= (uint32_t)ws.cap;
     uint32_t c = 0;
     if ((reinterpret_cast<uintptr_t>(words) & 15u) == 0) {
       // 16-byte loads of 8 words per lane from the aligned word at or before w0
@@ -154,14 +175,6 @@ __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict
   return st;
 }
 
-// The layer's sector positions and the weight table to LDS (lookups of every hit of the unit).
-__device__ inline void stage_tables(const Geom& g, int layer, const WaveScratch& ws) {
-  const int lane = lane_id();
-  for (int s = lane; s < g.S; s += kWave) ws.u0[s] = g.u0[layer * g.S + s];
-  if (lane < 16) ws.wt[lane] = g.weight_by_size[lane];
-  wave_sync();
-}
-
 // Decode one raw word of sector s in layer `layer`.
 struct DecodedHit {
   uint32_t lhcbid;
@@ -177,14 +190,14 @@ __device__ inline DecodedHit decode_word(const Geom& g, int layer, uint32_t s, u
   return d;
 }
 
-__device__ inline void store_hit(const Geom& g, int layer, const DecodedHit& d, int64_t h,
+__device__ inline void store_hit(const Geom& g, float z, const DecodedHit& d, int64_t h,
                                  int64_t capacity, const HitsOut& out, uint32_t* flags) {
   if (h >= capacity) {
     raise_flag(flags, UTC_FLAG_CAPACITY);
     return;
   }
   out.lhcbid[h] = d.lhcbid;
-  if (out.z) out.z[h] = g.z_layer[layer];   // the layer constants are optional outputs
+  if (out.z) out.z[h] = z;   // the layer constants are optional outputs
   out.u[h] = d.u;
   if (out.y_begin) out.y_begin[h] = g.y_begin;
   if (out.y_end) out.y_end[h] = g.y_end;
@@ -194,10 +207,10 @@ __device__ inline void store_hit(const Geom& g, int layer, const DecodedHit& d, 
 // A bank too large for the LDS chunk: rank every hit against the whole bank in global memory.
 __device__ inline uint32_t big_bank(const Geom& g, const uint16_t* __restrict__ words, int layer,
                                     uint32_t s, uint32_t a, uint32_t n, int64_t first_hit,
-                                    int64_t capacity, const HitsOut& out, uint32_t* flags,
-                                    float* lds_u, float* lds_w, uint32_t lds_first)
+                                    int64_t capacity, const HitsOut& out, uint32_t* flags)
 {
   const int lane = lane_id();
+  const float z_l = g.z_layer[layer];
   uint32_t nh = 0;
   for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
     const uint32_t i = i0 + lane;
@@ -213,25 +226,23 @@ __device__ inline uint32_t big_bank(const Geom& g, const uint16_t* __restrict__ 
       rank += ((o & 0xFu) != 0u) & ((o < v) | ((o == v) & (j < i)));
     }
     const DecodedHit d = decode_word(g, layer, s, v);
-    store_hit(g, layer, d, first_hit + rank, capacity, out, flags);
-    if (lds_u) {
-      lds_u[lds_first + rank] = d.u;
-      lds_w[lds_first + rank] = d.w;
-    }
+    store_hit(g, z_l, d, first_hit + rank, capacity, out, flags);
   }
   return nh;
 }
 
-// Compaction, sort and store of the unit's hits, first hit `base`.  When lds_u is given,
-// u and weight of hit k of the unit are also written to lds_u/lds_w[lds_first + k].
+// Compaction, sort and store of the unit's hits, first hit `base`.
 __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ words, int layer,
                                   int64_t b0, uint32_t base, const UnitCount& st,
                                   const WaveScratch& ws, int64_t capacity,
                                   uint32_t* __restrict__ hit_offsets, const HitsOut& out,
-                                  uint32_t* flags, float* lds_u, float* lds_w, uint32_t lds_first)
+                                  uint32_t* flags)
 {
   const int S = g.S;
   const int lane = lane_id();
+  // read once here: an indexed read of the by-value geometry goes to kernel-argument memory, and
+  // inside the store loop it would be repeated (and waited for) after every store
+  const float z_l = g.z_layer[layer];
   uint32_t local = 0;
   int c0 = 0;
   while (c0 < S) {
@@ -243,15 +254,15 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
         ++c0;
         continue;
       }
-      c1 = e0 - a0 > (uint32_t)kCap ? c0 : c0 + 1;
+      c1 = e0 - a0 > (uint32_t)ws.cap ? c0 : c0 + 1;
     } else {
       // the longest run of banks from c0 whose words fit in the staging buffer
-      c1 = (int)first_true(c0 + 1, S + 1, [&](int64_t b) { return ws.off[b] - a0 > (uint32_t)kCap; }) - 1;
+      c1 = (int)first_true(c0 + 1, S + 1, [&](int64_t b) { return ws.off[b] - a0 > (uint32_t)ws.cap; }) - 1;
     }
     if (c1 == c0) {
       if (lane == 0) hit_offsets[b0 + c0] = base + local;
       local += big_bank(g, words, layer, (uint32_t)c0, a0, e0 - a0, (int64_t)base + local, capacity,
-                        out, flags, lds_u, lds_w, lds_first + local);
+                        out, flags);
       wave_sync();
       ++c0;
       continue;
@@ -353,11 +364,7 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       d.lhcbid = ((uint32_t)layer << 28) | ((uint32_t)bk << 12) | (strip << 3) | frac;
       d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0);
       d.w = w;
-      store_hit(g, layer, d, (int64_t)base + local + slot, capacity, out, flags);
-      if (lds_u) {
-        lds_u[lds_first + local + slot] = d.u;
-        lds_w[lds_first + local + slot] = d.w;
-      }
+      store_hit(g, z_l, d, (int64_t)base + local + slot, capacity, out, flags);
     }
     local += nh;
     c0 = c1;
