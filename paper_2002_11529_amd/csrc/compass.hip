@@ -159,7 +159,11 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   p.prune = 1;
   for (int l = 0; l < kLayers; ++l)
     if (!(geom->a_kick[l] > 0.0f) || !std::isfinite(geom->a_kick[l])) p.prune = 0;
-  const int block = launch ? launch->block : 256;
+  // without a given launch shape, fewer wavefronts per workgroup when the bank offsets of a large
+  // geometry and the tiles of large windows do not fit the LDS of four
+  int block = launch ? launch->block : 256;
+  while (!launch && block > kWave && compass_lds_bytes(g.S, p.max_hits, block / kWave, 0) > 160 * 1024)
+    block -= kWave;
   const int waves = block / kWave;
   // stage u of events up to u_cap hits, keeping the workgroup's LDS at 10 KiB per wavefront (four
   // 256-thread workgroups share a CU's 160 KiB, the occupancy the kernel's registers allow);

@@ -1,0 +1,101 @@
+"""GPU parity at the limits of the interface: the largest window (UTC_MAX_WINDOW_HITS slots), the
+largest geometry (8192 sectors per layer), a bank of exactly UTC_MAX_BANK_WORDS words, and an
+(event, layer) with more hits than 16-bit windows can address.  Every case is compared with the
+oracle element by element (decoded hits, offsets, windows, selected hits, q/p, chi2, flags)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import gpu_run, oracle_run, assert_decode_equal, assert_compass_equal
+
+pytestmark = pytest.mark.gpu
+
+MAX_WINDOW_HITS = 32
+MAX_BANK_WORDS = 8192
+MAX_SECTORS = 8192
+
+
+def _check(b, flags=0):
+    h, r, *_ = gpu_run(b)
+    d, c = oracle_run(b)
+    # the search raises its flags in the decoder's flag word
+    assert d["flags"] == flags & ~oracle.FLAG_LAYER_OVERFLOW
+    assert r["error_flags"] == (d["flags"] | c["flags"]) == flags
+    assert_decode_equal(h, d)
+    assert_compass_equal(r, c, b, d)
+    return d, c
+
+
+def test_full_32_hit_windows():
+    """Dense events and a low momentum cut: most windows hold the full 32 slots, so every bit of
+    the 32-bit slot masks is in use."""
+    b = synth.generate("tiny", n_events=6, seed=31, noise=("fixed", 20000), with_truth=False)
+    b.params = synth.make_compass_params(p_min_mev=150.0, max_hits=MAX_WINDOW_HITS, n_sectors_search=5)
+    print(f"[limits max window] events={b.n_events} tracks={b.n_tracks}", flush=True)
+    d, c = _check(b)
+    assert (c["win_size"] == MAX_WINDOW_HITS).mean() > 0.5
+    assert (c["nhits"] > 0).mean() > 0.9
+
+
+@pytest.mark.parametrize("max_hits", [8, MAX_WINDOW_HITS])
+def test_largest_geometry(max_hits):
+    """8192 sectors per layer: the bank offsets of an event fill most of the LDS, the decoder and
+    the search shrink their workgroups to fit."""
+    b = synth.generate("tiny", n_events=3, seed=32, n_sectors=MAX_SECTORS, with_truth=False)
+    b.params = synth.make_compass_params(p_min_mev=float(b.params.p_min), max_hits=max_hits,
+                                         n_sectors_search=5)
+    print(f"[limits S={MAX_SECTORS} M={max_hits}] events={b.n_events} tracks={b.n_tracks}", flush=True)
+    d, c = _check(b)
+    assert (c["nhits"] > 0).mean() > 0.9
+
+
+def test_bank_of_the_largest_size():
+    """A bank of exactly UTC_MAX_BANK_WORDS words is decoded (sorted against the whole bank in
+    global memory), not flagged."""
+    b = synth.generate("tiny", n_events=2, seed=33, with_truth=False)
+    S = b.detector.n_sectors
+    bank = (1 * 4 + 2) * S + 7          # event 1, layer 2, sector 7
+    off = b.bank_offsets.astype(np.int64)
+    have = int(off[bank + 1] - off[bank])
+    rng = np.random.default_rng(5)
+    n = MAX_BANK_WORDS - have
+    strip = rng.integers(0, 512, n)
+    frac = rng.integers(0, 8, n)
+    size = np.where(rng.random(n) < 0.1, 0, rng.integers(1, 16, n))   # 10 % padding
+    extra = ((strip << 7) | (frac << 4) | size).astype(np.uint16)
+    b.words = np.concatenate([b.words[:off[bank + 1]], extra, b.words[off[bank + 1]:]])
+    off[bank + 1:] += n
+    b.bank_offsets = off.astype(np.uint32)
+    assert int(off[bank + 1] - off[bank]) == MAX_BANK_WORDS
+    print(f"[limits bank] words={b.n_words}", flush=True)
+    _check(b)
+
+
+def test_layer_beyond_16_bit_windows():
+    """Event 0, layer 0 holds 40000 hits (five banks of 8000): the search flags the overflow and
+    gives that event's tracks no candidates; the other event is searched as usual."""
+    b = synth.generate("tiny", n_events=2, seed=34, with_truth=False)
+    S = b.detector.n_sectors
+    off = b.bank_offsets.astype(np.int64)
+    rng = np.random.default_rng(6)
+    parts, last = [], 0
+    new_off = off.copy()
+    added = 0
+    for bank in range(5):              # event 0, layer 0, sectors 0..4
+        parts.append(b.words[last:off[bank + 1]])
+        n = 8000 - int(off[bank + 1] - off[bank])
+        strip = rng.integers(0, 512, n)
+        frac = rng.integers(0, 8, n)
+        parts.append(((strip << 7) | (frac << 4) | 1).astype(np.uint16))
+        added += n
+        new_off[bank + 1] += added
+        last = int(off[bank + 1])
+    parts.append(b.words[last:])
+    new_off[6:] = off[6:] + added
+    b.words = np.concatenate(parts)
+    b.bank_offsets = new_off.astype(np.uint32)
+    print(f"[limits layer overflow] words={b.n_words}", flush=True)
+    d, c = _check(b, flags=oracle.FLAG_LAYER_OVERFLOW)
+    t0 = int(b.velo_offsets[1])
+    assert not c["active"][:t0].any() and (c["nhits"][t0:] > 0).mean() > 0.9
