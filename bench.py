@@ -22,6 +22,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 vector instruction per SIMD every 4 cycles
+# (16 lanes per SIMD), at the 2.4 GHz peak engine clock
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 KERNEL_OF_CALL = {"ut_decode": "k_decode", "compass_find": "k_compass", "compass_fit_grad": "k_fitgrad"}
 # sources each kernel is compiled from: counters taken before a change to any of them no longer apply
 KERNEL_SOURCES = {
@@ -48,11 +51,10 @@ def kernel_source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary of the workload
-    (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain copy of known size), or
-    None when there is none or it was taken from other kernel sources than the current ones."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.txt")
+def counter_fields(kernel, workload, what):
+    """Fields of the committed counter summary profiles/{workload}_{what}_counters.txt, or None
+    when there is none or it was taken from other kernel sources than the current ones."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{what}_counters.txt")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -63,8 +65,24 @@ def measured_traffic(kernel, workload):
                 fields[k.strip()] = v.strip()
     if fields.get(f"{kernel}.source_sha256_16") != kernel_source_hash(kernel):
         return None
+    return fields
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a
+    plain copy of known size), or None (no summary, or one of other kernel sources)."""
+    fields = counter_fields(kernel, workload, "hbm")
     try:
-        return int(fields[f"{kernel}.hbm_bytes_per_launch"])
+        return int(fields[f"{kernel}.hbm_bytes_per_launch"]) if fields else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_valu(kernel, workload):
+    """Vector-ALU instructions (wave64) per launch of `kernel` (SQ_INSTS_VALU), or None."""
+    fields = counter_fields(kernel, workload, "sq")
+    try:
+        return int(fields[f"{kernel}.valu_instr_per_launch"]) if fields else None
     except (KeyError, ValueError):
         return None
 
@@ -83,6 +101,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
+    ap.add_argument("--no-copy-bandwidth", action="store_true",
+                    help="skip the 1 GiB device copy that measures the card's streaming bandwidth")
     ap.add_argument("--no-compact", action="store_true",
                     help="skip the step timed on the compact hit form (no per-hit z / y range)")
     ap.add_argument("--no-fitgrad", action="store_true",
@@ -299,7 +319,7 @@ def main():
     dom = int(np.argmax(call_ms))
     achieved = per_call_bytes[dom] / (call_ms[dom] * 1e-3) / 1e9
     value = E / (ms_per_step * 1e-3)
-    copy_bw = copy_bandwidth()
+    copy_bw = None if args.no_copy_bandwidth else copy_bandwidth()
 
     out = {
         "metric": "events/s UT decode+Compass @1 GPU (HBM GB/s); fwd+bwd fitted tracks/s",
@@ -322,7 +342,9 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload),
-                     "copy_GBps": round(copy_bw, 1), "frac_of_copy": round(achieved / copy_bw, 4)},
+                     "copy_GBps": round(copy_bw, 1) if copy_bw else None,
+                     "frac_of_copy": round(achieved / copy_bw, 4) if copy_bw else None,
+                     "valu_issue": valu_issue(KERNEL_OF_CALL[names[dom]], args.workload, call_ms[dom])},
         "calls_ms": {n: round(float(m), 5) for n, m in zip(names, call_ms)},
         "step_algorithmic_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "decode_GBps": round(bytes_decode / (call_ms[0] * 1e-3) / 1e9, 1),
@@ -438,6 +460,17 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n, "bytes_written": n, "copies": 5}), flush=True)
+
+
+def valu_issue(kernel, workload, ms):
+    """The kernel's measured vector-instruction rate against the VALU issue ceiling, the bound the
+    search and decode kernels actually run into (None without a current counter summary)."""
+    n = measured_valu(kernel, workload)
+    if n is None:
+        return None
+    rate = n / (ms * 1e-3)
+    return {"instr_per_launch": n, "achieved_instr_per_s": round(rate, -6),
+            "peak_instr_per_s": VALU_ISSUE_PEAK, "frac": round(rate / VALU_ISSUE_PEAK, 4)}
 
 
 def copy_bandwidth(reps=10):
