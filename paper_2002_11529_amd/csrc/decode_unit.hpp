@@ -231,6 +231,15 @@ __device__ inline uint32_t big_bank(const Geom& g, const uint16_t* __restrict__ 
   return nh;
 }
 
+// Number of the n keys at k below `mine`.
+template <int N>
+__device__ inline uint32_t count_below(const uint32_t* k, uint32_t mine) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) r += (uint32_t)(k[q] < mine);
+  return r;
+}
+
 // Compaction, sort and store of the unit's hits, first hit `base`.
 __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ words, int layer,
                                   int64_t b0, uint32_t base, const UnitCount& st,
@@ -352,12 +361,22 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       const float u0 = ws.u0[bk];
       const float w = ws.wt[v & 0xFu];
       const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
+      // keys of the bank below this hit's, compared 16, 8 and 4 at a time (independent LDS reads
+      // in flight; the central banks of an event hold tens of hits), then the last up to three
       uint32_t rank = 0;
       uint32_t j = lo;
-      for (; j + 4 <= hi; j += 4)
-        rank += (uint32_t)(ws.key[j] < mine) + (uint32_t)(ws.key[j + 1] < mine) +
-                (uint32_t)(ws.key[j + 2] < mine) + (uint32_t)(ws.key[j + 3] < mine);
-      for (; j < hi; ++j) rank += ws.key[j] < mine;
+      for (; j + 16 <= hi; j += 16) rank += count_below<16>(ws.key + j, mine);
+      if (j + 8 <= hi) {
+        rank += count_below<8>(ws.key + j, mine);
+        j += 8;
+      }
+      if (j + 4 <= hi) {
+        rank += count_below<4>(ws.key + j, mine);
+        j += 4;
+      }
+      if (j < hi) rank += ws.key[j] < mine;
+      if (j + 1 < hi) rank += ws.key[j + 1] < mine;
+      if (j + 2 < hi) rank += ws.key[j + 2] < mine;
       const uint32_t slot = lo + rank;
       const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
       DecodedHit d;
