@@ -168,7 +168,7 @@ utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks, const in
  * Autotuning of the batched launch (not in the paper, which tuned its kernel parameters by hand,
  * Section VI-C).  Each call runs the matching entry point on the caller's buffers (same arguments
  * and meaning as ut_decode / compass_find) for every candidate launch shape: block in
- * {64, 128, 256, 512} (decode) or {64, 128, 256} (Compass), grid in {one workgroup per work
+ * {64, 128, 256, 512} (decode and Compass), grid in {one workgroup per work
  * item, 256 .. 2048 persistent workgroups}; each shape runs once to warm up and then `reps` times
  * (1..32).  *best receives the shape with the lowest median time, *best_us that time in
  * microseconds.  Results do not depend on the shape.  Unlike the other calls these synchronise

@@ -89,7 +89,7 @@ extern "C" utc_status compass_find_autotune(const utc_geometry* geom, const utc_
                                             hipStream_t stream)
 {
   if (!best || !best_us) return UTC_ERR_ARG;
-  static const int blocks[] = {64, 128, 256};
+  static const int blocks[] = {64, 128, 256, 512};
   static const int grids[] = {0, 512, 1024, 2048};
   Timer tm;
   float t_best = 3.0e38f;

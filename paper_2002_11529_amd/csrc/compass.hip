@@ -13,7 +13,7 @@ namespace utc {
 // kGreedy: the paper's search variant (max_tracklets > 0), a kernel of its own so that its code
 // does not weigh on the register allocation of the default search
 template <bool kGreedy>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
           const float* __restrict__ hu, const float* __restrict__ hw,
           const float* __restrict__ hyb, const float* __restrict__ hye,
@@ -142,7 +142,7 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
                        !chi2 || !nhits))
     return UTC_ERR_ARG;
   if ((hit_y_begin == nullptr) != (hit_y_end == nullptr)) return UTC_ERR_ARG;
-  if (launch && (launch->block < 64 || launch->block > 256 || launch->block % 64 || launch->grid < 0))
+  if (launch && (launch->block < 64 || launch->block > 512 || launch->block % 64 || launch->grid < 0))
     return UTC_ERR_ARG;
   if (!workspace || workspace_bytes < compass_find_workspace_bytes(n_events, n_tracks))
     return UTC_ERR_WORKSPACE;

@@ -56,7 +56,8 @@ def test_persistent_shapes_equal(uneven):
     h0, r0 = _batched(b, dv, geom)
     n = int(h0["hit_offsets"][-1])
     for ld, lf in ((dict(block=128, grid=5), dict(block=64, grid=3)),
-                   (dict(block=512, grid=256), dict(block=256, grid=1024))):
+                   (dict(block=512, grid=256), dict(block=256, grid=1024)),
+                   (dict(block=64), dict(block=512)), (dict(block=256), dict(block=512, grid=7))):
         h1, r1 = _batched(b, dv, geom, ld, lf)
         assert torch.equal(h0["hit_offsets"], h1["hit_offsets"])
         assert torch.equal(h0["u"][:n], h1["u"][:n]) and torch.equal(h0["lhcbid"][:n], h1["lhcbid"][:n])
@@ -69,7 +70,7 @@ def test_autotune_choice_is_valid_and_equal(uneven, tmp_path, monkeypatch):
     monkeypatch.setenv("UTC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     t = utc.autotune(geom, b.params, b.n_events, dv["words"], dv["bank_offsets"], *dv["vel"],
                      dv["velo_offsets"], reps=2)
-    assert t["decode"]["block"] in (64, 128, 256, 512) and t["find"]["block"] in (64, 128, 256)
+    assert t["decode"]["block"] in (64, 128, 256, 512) and t["find"]["block"] in (64, 128, 256, 512)
     assert t["decode_us"] > 0 and t["find_us"] > 0
     again = utc.autotune(geom, b.params, b.n_events, dv["words"], dv["bank_offsets"], *dv["vel"],
                          dv["velo_offsets"], reps=2)
