@@ -101,6 +101,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="consecutive steps go to this many streams in turn (independent batches in flight "
+                         "at once); every buffer copy stays on one stream")
     ap.add_argument("--no-copy-bandwidth", action="store_true",
                     help="skip the 1 GiB device copy that measures the card's streaming bandwidth")
     ap.add_argument("--no-compact", action="store_true",
@@ -143,7 +146,8 @@ def main():
     params = utc.compass_params(b.params)
     L = utc.library()
 
-    R = max(1, args.rotate)
+    NS = max(1, args.streams)
+    R = -(-max(1, args.rotate, NS) // NS) * NS   # a multiple of the stream count
     copies = []
     for _ in range(R):
         words = torch.from_numpy(b.words.view(np.int16).copy()).to(dev)
@@ -165,12 +169,14 @@ def main():
                   chi2_track=torch.empty(n, dtype=torch.float32, device=dev),
                   grad_qop=torch.empty(n, dtype=torch.float32, device=dev),
                   grad_offsets=torch.empty(4 * S, dtype=torch.float32, device=dev))
-        copies.append(dict(words=words, boff=boff, vel=vel, vo=vo, hits=hits, res=res, fg=fg))
+        # workspaces per copy: steps on different streams may run at the same time
+        ws = dict(dec=torch.empty(L.ut_decode_workspace_bytes(E, S), dtype=torch.uint8, device=dev),
+                  find=torch.empty(max(256, L.compass_find_workspace_bytes(E, b.n_tracks)),
+                                   dtype=torch.uint8, device=dev),
+                  fg=torch.empty(L.compass_fit_grad_workspace_bytes(S), dtype=torch.uint8, device=dev))
+        copies.append(dict(words=words, boff=boff, vel=vel, vo=vo, hits=hits, res=res, fg=fg, ws=ws))
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     offsets = torch.zeros(4 * S, dtype=torch.float32, device=dev)
-    ws_dec = torch.empty(L.ut_decode_workspace_bytes(E, S), dtype=torch.uint8, device=dev)
-    ws_find = torch.empty(max(256, L.compass_find_workspace_bytes(E, b.n_tracks)), dtype=torch.uint8, device=dev)
-    ws_fg = torch.empty(L.compass_fit_grad_workspace_bytes(S), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     tuned = None
     if not args.no_autotune:
@@ -187,16 +193,16 @@ def main():
         if ev is not None:
             ev[0].record(stream)
         utc.ut_decode(geom, c["words"], c["boff"], E, hit_capacity=b.n_words, error_flags=flags,
-                      out=hits, workspace=ws_dec, launch=lau_dec)
+                      out=hits, workspace=c["ws"]["dec"], launch=lau_dec)
         if ev is not None:
             ev[1].record(stream)
         utc.compass_find(geom, params, E, hits, *c["vel"], c["vo"], error_flags=flags,
-                         out=c["res"], workspace=ws_find, launch=lau_find)
+                         out=c["res"], workspace=c["ws"]["find"], launch=lau_find)
         if ev is not None:
             ev[2].record(stream)
         utc.compass_fit_grad(geom, c["res"]["hit_idx"], hits["u"], hits["weight"],
                              hits["lhcbid"], *c["vel"], c["res"]["qop"], offsets,
-                             out=c["fg"], workspace=ws_fg)
+                             out=c["fg"], workspace=c["ws"]["fg"])
         if ev is not None:
             ev[3].record(stream)
 
@@ -236,17 +242,23 @@ def main():
             graphs[i % R].replay()
         torch.cuda.synchronize()
 
-    # timed region: K whole steps, bracketed by synchronisation
+    # timed region: K whole steps, bracketed by synchronisation; step i runs on stream i % NS
+    streams = [stream] + [torch.cuda.Stream() for _ in range(NS - 1)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record(stream)
+    for st in streams[1:]:
+        st.wait_stream(stream)
     for i in range(K):
-        if graphs is not None:
-            graphs[i % R].replay()
-        else:
-            step(copies[i % R])
+        with torch.cuda.stream(streams[i % NS]):
+            if graphs is not None:
+                graphs[i % R].replay()
+            else:
+                step(copies[i % R])
+    for st in streams[1:]:
+        stream.wait_stream(st)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -337,7 +349,7 @@ def main():
         "config": {"workload": f"{args.workload}: {E} events, {S} sectors/layer, {Nt} VELO tracks, "
                                f"{Nh} hits, {Nw} raw words",
                    "step": "ut_decode + compass_find + compass_fit_grad(fwd+bwd)",
-                   "rotated_copies": R},
+                   "rotated_copies": R, "streams": NS},
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
