@@ -75,9 +75,10 @@ typedef struct {
                                 N tracklets */
 } utc_compass_params;
 
-/* Launch shape.  NULL selects the defaults.  block: threads per workgroup (64..1024, multiple of
- * 64); grid: workgroups (0 = one per work item, > 0 = persistent grid of that many workgroups
- * taking work items from a queue). */
+/* Launch shape.  NULL selects the defaults.  block: threads per workgroup, a multiple of 64, at
+ * most 1024 for ut_decode and 512 for compass_find (a shape outside these limits, or one whose LDS
+ * does not fit a CU, is rejected with UTC_ERR_ARG); grid: workgroups (0 = one per work item, > 0 =
+ * persistent grid of that many workgroups striding over the work items). */
 typedef struct {
   int32_t block;
   int32_t grid;
