@@ -1,5 +1,6 @@
 """Parity at the workloads' full sizes, in the autotuned launch shapes that the benchmark times.
 
+* realistic: 1000 events (200 sectors): every decoded hit and every track against the oracle.
 * batched: 20000 uneven events (32 sectors): every decoded hit and every track against the oracle.
 * pileup: 10000 high-occupancy events (200 sectors, 16-hit windows): every output of 600 sampled
   events (seeded, plus the largest and the smallest event) against the oracle run on those events
@@ -58,6 +59,23 @@ def _common_properties(b, hits, res):
         sel = idx[:, l] >= 0
         assert np.all((idx[sel, l] >= lo[sel]) & (idx[sel, l] < hi[sel])), l
     return nh
+
+
+def test_realistic_full_every_output():
+    b = synth.generate("realistic", with_truth=False)
+    geom, dv, hits, res = _run_tuned(b)
+    _common_properties(b, hits, res)
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    c = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx, b.velo_ty,
+                       b.velo_offsets)
+    n = int(d["hit_offsets"][-1])
+    assert np.array_equal(_u32(hits["hit_offsets"]), d["hit_offsets"])
+    for k in ("lhcbid", "u", "weight", "z", "y_begin", "y_end"):
+        assert np.array_equal(_u32(hits[k])[:n], d[k][:n].view(np.uint32)), k
+    assert np.array_equal(res["hit_idx"].cpu().numpy(), c["hit_idx"])
+    assert np.array_equal(res["nhits"].cpu().numpy(), c["nhits"])
+    for k in ("qop", "chi2"):
+        assert np.array_equal(_u32(res[k]), c[k].view(np.uint32)), k
 
 
 def test_batched_full_every_output():
