@@ -3,7 +3,7 @@
 * windows: a linear scan over every hit of the allowed sectors (found through the LHCbID, not the
   offsets array) must give the same hit set, and a capped window must hold the hits nearest to the
   prediction;
-* tracklets: every combination of one window hit or none per layer with at least three hits, judged
+* tracklets: every combination of one window hit or none per layer with at least three hits, assessed
   by the candidate predicate and the selection order, must give the oracle's choice;
 * fit: hits placed exactly on the single-kick model give back the generated q/p, and the one-
   parameter weighted least squares agrees with numpy.linalg.lstsq;
