@@ -84,3 +84,82 @@ def test_host_argument_errors_return_without_launching():
                           None) == -1
     assert L.compass_fit_grad(ctypes.byref(g), -1, None, 0, None, None, None, None, None, None,
                               None, None, None, 1.0, None, None, None, None, None, 0, None) == -1
+
+
+def test_host_checks_of_every_entry_point():
+    """Launch-shape limits, the pointer rules of the compact hit form, parameter ranges and workspace
+    sizes are checked on the host before anything is enqueued (none of these calls reaches the GPU;
+    placeholder pointers are never dereferenced)."""
+    import synth
+    import paper_2002_11529_amd.api as api
+    L = api.library()
+    g = api.UtcGeometry()
+    g.n_layers, g.n_sectors, g.u0 = 4, 32, 16
+    one = ctypes.c_void_p(64)
+    ws_dec = L.ut_decode_workspace_bytes(1, 32)
+
+    def decode(launch=None, z=one, yb=one, ye=one, ws=None, ws_bytes=0, n_events=1):
+        return L.ut_decode(ctypes.byref(g), one, one, n_events, 10, one, one, z, one, yb, ye, one, None,
+                           ws, ws_bytes, ctypes.byref(launch) if launch else None, None)
+
+    # the compact form: z, y_begin, y_end may be NULL (the call gets as far as the workspace check)
+    assert decode(z=None, yb=None, ye=None) == -2
+    # launch shapes: block a multiple of 64 in [64, 1024]
+    for block, ok in ((32, False), (96, False), (1088, False), (64, True), (1024, True)):
+        lc = api.UtcLaunchConfig()
+        lc.block, lc.grid = block, 0
+        assert decode(launch=lc) == (-2 if ok else -1), block
+    lc = api.UtcLaunchConfig()
+    lc.block, lc.grid = 256, -1
+    assert decode(launch=lc) == -1
+    # workspace one byte short
+    assert decode(ws=one, ws_bytes=ws_dec - 1) == -2
+
+    p = api.compass_params(synth.make_compass_params())
+
+    def find(launch=None, yb=one, ye=one, ws=one, ws_bytes=256, n_tracks=1, n_events=1):
+        return L.compass_find(ctypes.byref(g), ctypes.byref(p), n_events, one, one, one, yb, ye, one,
+                              one, one, one, one, n_tracks, one, one, one, one, None, None, ws,
+                              ws_bytes, ctypes.byref(launch) if launch else None, None)
+
+    # nothing to do: returns ok without launching
+    assert find(n_tracks=0) == 0 and find(n_events=0) == 0
+    # per-hit y ranges: both or neither
+    assert find(n_tracks=0, yb=None, ye=None) == 0
+    assert find(yb=None) == -1 and find(ye=None) == -1
+    assert find(ws=None) == -2 and find(ws_bytes=8) == -2
+    for block, ok in ((576, False), (1024, False), (512, True), (64, True)):
+        lc = api.UtcLaunchConfig()
+        lc.block, lc.grid = block, 0
+        assert (find(launch=lc, n_tracks=0) == 0) == ok, block
+    for field, bad in (("max_hits", 0), ("max_hits", 33), ("n_sectors_search", 2), ("max_tracklets", -1)):
+        q = api.compass_params(synth.make_compass_params())
+        setattr(q, field, bad)
+        assert L.compass_find(ctypes.byref(g), ctypes.byref(q), 1, one, one, one, one, one, one, one,
+                              one, one, one, 0, one, one, one, one, None, None, one, 256, None,
+                              None) == -1, field
+
+    # fit gradient: workspace sized for the geometry
+    need = L.compass_fit_grad_workspace_bytes(32)
+    args = [ctypes.byref(g), 1, one, 4, one, one, one, one, one, one, one, one, one, 1.0, one, one, one,
+            one]
+    assert L.compass_fit_grad(*args, one, need - 1, None) == -2
+    assert L.compass_fit_grad(*args, None, need, None) == -2
+    bad = list(args)
+    bad[2] = None                      # track_hit_idx missing
+    assert L.compass_fit_grad(*bad, one, need, None) == -1
+
+    # global event cut and consolidation
+    cut_ws = L.ut_global_event_cut_workspace_bytes(3)
+    cut = lambda n_events, ws, ws_bytes, words=one: L.ut_global_event_cut(
+        ctypes.byref(g), n_events, words, one, one, one, one, one, one, 100, one, one, one, one, one, one,
+        one, one, one, None, ws, ws_bytes, None)
+    assert cut(-1, one, cut_ws) == -1
+    assert cut(3, one, cut_ws, words=None) == -1
+    assert cut(3, one, cut_ws - 1) == -2
+    cons_ws = L.compass_consolidate_workspace_bytes(10)
+    cons = lambda n_tracks, ws_bytes, nhits=one: L.compass_consolidate(
+        2, one, n_tracks, nhits, one, one, one, one, one, one, one, one, one, one, one, ws_bytes, None)
+    assert cons(-1, cons_ws) == -1
+    assert cons(10, cons_ws, nhits=None) == -1
+    assert cons(10, cons_ws - 1) == -2
