@@ -111,10 +111,11 @@ __global__ void k_gec_copy(const uint16_t* __restrict__ words, const uint32_t* _
 
 // ---- consolidation ----
 
-constexpr int kConsItems = 4;   // tracks per thread in the consolidation kernels
+constexpr int kConsItems = 2;     // tracks per thread in the consolidation kernels
+constexpr int kConsThreads = 256; // threads per workgroup: many workgroups even for 1e5 tracks
 
-// Found tracks of each block of 1024 * kConsItems tracks.
-__global__ void __launch_bounds__(1024)
+// Found tracks of each block of kConsThreads * kConsItems tracks.
+__global__ void __launch_bounds__(kConsThreads)
 k_cons_count(const int32_t* __restrict__ nhits, int64_t n_tracks, uint32_t* __restrict__ block_sum) {
   __shared__ uint32_t tmp[17];
   const int64_t t0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kConsItems;
@@ -136,8 +137,9 @@ k_cons_scan(uint32_t* __restrict__ block_sum, int64_t n_blocks, uint32_t* __rest
 }
 
 // Scatter of the found tracks to their dense slots; the dense position of every track (found or
-// not) is kept for the per-event offsets.
-__global__ void __launch_bounds__(1024)
+// not) is kept for the per-event offsets.  hit_idx rows move as one 16-byte vector when both
+// arrays are 16-byte aligned.
+__global__ void __launch_bounds__(kConsThreads)
 k_cons_scatter(const int32_t* __restrict__ nhits, const int32_t* __restrict__ hit_idx,
                const float* __restrict__ qop, const float* __restrict__ chi2, int64_t n_tracks,
                const uint32_t* __restrict__ block_base, uint32_t* __restrict__ pos,
@@ -154,14 +156,19 @@ k_cons_scatter(const int32_t* __restrict__ nhits, const int32_t* __restrict__ hi
   }
   uint32_t tot;
   uint32_t p = block_base[blockIdx.x] + block_exclusive_scan(c, tmp, &tot);
+  const bool vec = ((reinterpret_cast<uintptr_t>(hit_idx) | reinterpret_cast<uintptr_t>(out_hit_idx)) & 15u) == 0;
 #pragma unroll
   for (int k = 0; k < kConsItems; ++k) {
     const int64_t t = t0 + k;
     if (t >= n_tracks) break;
     pos[t] = p;
     if (f[k]) {
+      if (vec) {
+        reinterpret_cast<int4*>(out_hit_idx)[p] = reinterpret_cast<const int4*>(hit_idx)[t];
+      } else {
 #pragma unroll
-      for (int l = 0; l < kLayers; ++l) out_hit_idx[4 * (int64_t)p + l] = hit_idx[4 * t + l];
+        for (int l = 0; l < kLayers; ++l) out_hit_idx[4 * (int64_t)p + l] = hit_idx[4 * t + l];
+      }
       out_velo[p] = (int32_t)t;
       out_qop[p] = qop[t];
       out_chi2[p] = chi2[t];
@@ -236,7 +243,7 @@ extern "C" utc_status ut_global_event_cut(const utc_geometry* geom, int32_t n_ev
 extern "C" size_t compass_consolidate_workspace_bytes(int64_t n_tracks)
 {
   if (n_tracks < 0) return 0;
-  const int64_t per_block = 1024 * kConsItems;
+  const int64_t per_block = kConsThreads * kConsItems;
   const int64_t blocks = (n_tracks + per_block - 1) / per_block;
   return (((size_t)n_tracks + (size_t)blocks + 2) * sizeof(uint32_t) + 255) / 256 * 256;
 }
@@ -254,16 +261,17 @@ extern "C" utc_status compass_consolidate(int32_t n_events, const uint32_t* velo
     return UTC_ERR_ARG;
   if (!workspace || workspace_bytes < compass_consolidate_workspace_bytes(n_tracks)) return UTC_ERR_WORKSPACE;
   (void)hipGetLastError();  // report only errors of this call
-  const int64_t per_block = 1024 * kConsItems;
+  const int64_t per_block = kConsThreads * kConsItems;
   const int64_t blocks = (n_tracks + per_block - 1) / per_block;
   uint32_t* pos = static_cast<uint32_t*>(workspace);   // [n_tracks]
   uint32_t* block_sum = pos + n_tracks;                // [blocks]
   uint32_t* total = block_sum + blocks;                // [1]
   if (blocks > 0)
-    hipLaunchKernelGGL(k_cons_count, dim3((unsigned)blocks), dim3(1024), 0, stream, nhits, n_tracks, block_sum);
+    hipLaunchKernelGGL(k_cons_count, dim3((unsigned)blocks), dim3(kConsThreads), 0, stream, nhits, n_tracks,
+                       block_sum);
   hipLaunchKernelGGL(k_cons_scan, dim3(1), dim3(1024), 0, stream, block_sum, blocks, total, n_found);
   if (blocks > 0)
-    hipLaunchKernelGGL(k_cons_scatter, dim3((unsigned)blocks), dim3(1024), 0, stream, nhits, hit_idx, qop,
+    hipLaunchKernelGGL(k_cons_scatter, dim3((unsigned)blocks), dim3(kConsThreads), 0, stream, nhits, hit_idx, qop,
                        chi2, n_tracks, block_sum, pos, out_velo, out_hit_idx, out_qop, out_chi2, out_nhits);
   hipLaunchKernelGGL(k_cons_offsets, dim3((n_events + 1 + 255) / 256), dim3(256), 0, stream, velo_offsets,
                      n_events, n_tracks, pos, total, out_offsets);
