@@ -31,31 +31,43 @@ k_decode_count(Geom g, const uint16_t* __restrict__ words, const uint32_t* __res
   }
 }
 
-// One workgroup: exclusive scan of the unit sums into the first hit of every unit.
+// One workgroup: exclusive scan of the unit sums into the first hit of every unit.  Each wave scans
+// kScanRows consecutive rows of 64 values (coalesced loads, a DPP scan per row carried along the
+// rows), the wave totals are scanned across the workgroup, and passes of 64 * kScanRows * waves
+// values follow each other.
+constexpr int kScanRows = 16;
+
 __global__ void __launch_bounds__(1024)
 k_decode_scan(const uint32_t* __restrict__ unit_sum, int n_units, uint32_t* __restrict__ unit_base,
               uint32_t* __restrict__ hit_offsets_end)
 {
-  constexpr int kItems = 16;
   __shared__ uint32_t tmp[kScanTmp];
-  uint32_t carry = 0;
-  for (int base = 0; base < n_units; base += blockDim.x * kItems) {
-    const int i0 = base + threadIdx.x * kItems;
-    uint32_t v[kItems];
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  uint32_t carry = 0;   // all values of the previous passes
+  for (int64_t base = 0; base < n_units; base += (int64_t)nw * kWave * kScanRows) {
+    const int64_t seg = base + (int64_t)wid * kWave * kScanRows;
+    uint32_t v[kScanRows], ex[kScanRows];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) v[k] = (i0 + k < n_units) ? unit_sum[i0 + k] : 0u;
-    uint32_t ex[kItems];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      ex[k] = sum;
-      sum += v[k];
+    for (int r = 0; r < kScanRows; ++r) {
+      const int64_t i = seg + r * kWave + lane;
+      v[r] = i < n_units ? unit_sum[i] : 0u;
     }
-    uint32_t tot;
-    const uint32_t pre = block_exclusive_scan(sum, tmp, &tot);
+    uint32_t run = 0;   // this wave's values before row r
 #pragma unroll
-    for (int k = 0; k < kItems; ++k)
-      if (i0 + k < n_units) unit_base[i0 + k] = carry + pre + ex[k];
+    for (int r = 0; r < kScanRows; ++r) {
+      const uint32_t x = wave_inclusive_scan(v[r]);
+      ex[r] = run + x - v[r];
+      run += (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
+    }
+    // the waves' totals (carried by their last lane) scanned across the workgroup
+    uint32_t tot;
+    const uint32_t woff = block_exclusive_scan(lane == kWave - 1 ? run : 0u, tmp, &tot);
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      const int64_t i = seg + r * kWave + lane;
+      if (i < n_units) unit_base[i] = carry + woff + ex[r];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) {
