@@ -5,28 +5,36 @@
 
 namespace utc {
 
-// Exclusive scan of n values in place by one workgroup (kItems per thread per pass); the total goes
-// to *total.  All threads of the workgroup must call it.
+// Exclusive scan of n values in place by one workgroup; the total goes to *total.  All threads of
+// the workgroup must call it.  Each wave scans kRows consecutive rows of 64 values (coalesced, a DPP
+// scan per row carried along the rows), then the wave totals are scanned across the workgroup.
 __device__ inline void block_scan_inplace(uint32_t* a, int64_t n, uint32_t* total, uint32_t* tmp) {
-  constexpr int kItems = 16;
+  constexpr int kRows = 16;
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
   uint32_t carry = 0;
-  for (int64_t base = 0; base < n; base += (int64_t)blockDim.x * kItems) {
-    const int64_t i0 = base + (int64_t)threadIdx.x * kItems;
-    uint32_t v[kItems];
+  for (int64_t base = 0; base < n; base += (int64_t)nw * kWave * kRows) {
+    const int64_t seg = base + (int64_t)wid * kWave * kRows;
+    uint32_t v[kRows], ex[kRows];
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) v[k] = (i0 + k < n) ? a[i0 + k] : 0u;
-    uint32_t ex[kItems];
-    uint32_t sum = 0;
+    for (int r = 0; r < kRows; ++r) {
+      const int64_t i = seg + r * kWave + lane;
+      v[r] = i < n ? a[i] : 0u;
+    }
+    uint32_t run = 0;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      ex[k] = sum;
-      sum += v[k];
+    for (int r = 0; r < kRows; ++r) {
+      const uint32_t x = wave_inclusive_scan(v[r]);
+      ex[r] = run + x - v[r];
+      run += (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
     }
     uint32_t tot;
-    const uint32_t pre = block_exclusive_scan(sum, tmp, &tot);
+    const uint32_t woff = block_exclusive_scan(lane == kWave - 1 ? run : 0u, tmp, &tot);
 #pragma unroll
-    for (int k = 0; k < kItems; ++k)
-      if (i0 + k < n) a[i0 + k] = carry + pre + ex[k];
+    for (int r = 0; r < kRows; ++r) {
+      const int64_t i = seg + r * kWave + lane;
+      if (i < n) a[i] = carry + woff + ex[r];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) *total = carry;
