@@ -151,7 +151,8 @@ utc_status compass_find(const utc_geometry* geom, const utc_compass_params* para
  * track_hit_idx[4t + l]: index into the hit arrays (length n_hits) of the layer-l hit of track t,
  * or -1; the sector of a hit is taken from its LHCbID.  Slots whose index is outside [0, n_hits) or
  * whose LHCbID names no sector of the geometry are skipped.  Every output may be NULL; a call with
- * all gradient pointers NULL is the forward pass.
+ * all gradient pointers NULL is the forward pass.  The sums are accumulated per workgroup in LDS up
+ * to 2559 sectors per layer and in the workspace beyond (same results).
  * Workspace: compass_fit_grad_workspace_bytes(S) bytes, any content.
  * --------------------------------------------------------------------------------------------- */
 size_t compass_fit_grad_workspace_bytes(int32_t n_sectors);

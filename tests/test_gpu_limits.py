@@ -99,3 +99,34 @@ def test_layer_beyond_16_bit_windows():
     d, c = _check(b, flags=oracle.FLAG_LAYER_OVERFLOW)
     t0 = int(b.velo_offsets[1])
     assert not c["active"][:t0].any() and (c["nhits"][t0:] > 0).mean() > 0.9
+
+
+def test_fit_gradient_on_the_largest_geometry():
+    """8192 sectors per layer: the 4S offset sums no longer fit in LDS and are accumulated in place
+    in the workspace; per-track terms bit for bit, sums within one ulp of the oracle's."""
+    import torch
+    import paper_2002_11529_amd as utc
+    from tests.gpu_helpers import DEV
+    b = synth.generate("tiny", n_events=20, seed=35, n_sectors=MAX_SECTORS, with_truth=False)
+    h, r, geom, hits, res, dv = gpu_run(b)
+    d, c = oracle_run(b)
+    keep = c["nhits"] >= 3
+    print(f"[limits fitgrad S={MAX_SECTORS}] tracks={int(keep.sum())}", flush=True)
+    kd = torch.from_numpy(keep).to(DEV)
+    rng = np.random.default_rng(7)
+    q = (c["qop"][keep].astype(np.float64) * (1 + rng.normal(0, 0.05, int(keep.sum())))).astype(np.float32)
+    off = rng.normal(0, 0.05, 4 * MAX_SECTORS).astype(np.float32)
+    g = utc.compass_fit_grad(geom, res["hit_idx"][kd].contiguous(), hits["u"], hits["weight"], hits["lhcbid"],
+                             *[v[kd].contiguous() for v in dv["vel"]], torch.from_numpy(q).to(DEV),
+                             torch.from_numpy(off).to(DEV), grad_scale=0.5)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    o = oracle.fit_grad(b.detector, c["hit_idx"][keep], d["u"], d["weight"], d["lhcbid"], b.velo_x[keep],
+                        b.velo_y[keep], b.velo_tx[keep], b.velo_ty[keep], q, off, grad_scale=0.5,
+                        precision="f32")
+    assert np.array_equal(g["chi2_track"].view(np.uint32), o["chi2_track"].view(np.uint32))
+    assert np.array_equal(g["grad_qop"].view(np.uint32), o["grad_qop"].view(np.uint32))
+    go, oo = g["grad_offsets"].astype(np.float64), o["grad_offsets"]
+    assert np.all(np.abs(go - oo) <= np.spacing(np.abs(oo)))
+    assert np.count_nonzero(oo) > 20
+    assert g["chi2_total"][0] == pytest.approx(o["chi2_total"], rel=1e-12)
