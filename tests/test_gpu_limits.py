@@ -130,3 +130,14 @@ def test_fit_gradient_on_the_largest_geometry():
     assert np.all(np.abs(go - oo) <= np.spacing(np.abs(oo)))
     assert np.count_nonzero(oo) > 20
     assert g["chi2_total"][0] == pytest.approx(o["chi2_total"], rel=1e-12)
+
+
+@pytest.mark.parametrize("n_search", [15, 65])
+def test_wide_sector_search(n_search):
+    """Searches over 15 sectors, and over more sectors than a layer has (the range is clamped)."""
+    b = synth.generate("tiny", n_events=10, seed=36, noise=("fixed", 3000), with_truth=False)
+    b.params = synth.make_compass_params(p_min_mev=float(b.params.p_min), max_hits=b.params.max_hits,
+                                         n_sectors_search=n_search)
+    print(f"[limits sectors searched {n_search}] tracks={b.n_tracks}", flush=True)
+    d, c = _check(b)
+    assert (c["nhits"] > 0).mean() > 0.9
