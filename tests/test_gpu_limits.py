@@ -141,3 +141,27 @@ def test_wide_sector_search(n_search):
     print(f"[limits sectors searched {n_search}] tracks={b.n_tracks}", flush=True)
     d, c = _check(b)
     assert (c["nhits"] > 0).mean() > 0.9
+
+
+def test_words_not_16_byte_aligned():
+    """A word buffer that starts 2 bytes past a 16-byte boundary takes the decoder's scalar loads;
+    the result is the same as from an aligned buffer (and the oracle's)."""
+    import torch
+    import paper_2002_11529_amd as utc
+    from tests.gpu_helpers import DEV, to_dev
+    b = synth.generate("realistic", n_events=40, seed=37, with_truth=False)
+    dv = to_dev(b)
+    geom = utc.Geometry(b.detector, DEV)
+    padded = torch.zeros(b.n_words + 1, dtype=torch.int16, device=DEV)
+    padded[1:] = dv["words"]
+    shifted = padded[1:]
+    assert shifted.data_ptr() % 16 == 2
+    ref = utc.ut_decode(geom, dv["words"], dv["bank_offsets"], b.n_events)
+    out = utc.ut_decode(geom, shifted, dv["bank_offsets"], b.n_events)
+    torch.cuda.synchronize()
+    n = int(ref["hit_offsets"][-1])
+    assert torch.equal(ref["hit_offsets"], out["hit_offsets"])
+    for k in ("lhcbid", "z", "u", "y_begin", "y_end", "weight"):
+        assert torch.equal(ref[k][:n], out[k][:n]), k
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    assert np.array_equal(out["u"][:n].cpu().numpy().view(np.uint32), d["u"][:n].view(np.uint32))
