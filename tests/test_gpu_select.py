@@ -103,3 +103,28 @@ def test_consolidate_empty():
     torch.cuda.synchronize()
     assert int(g["n_found"].item()) == 0
     assert not g["offsets"].cpu().numpy().any()
+
+
+def test_consolidate_unaligned_rows():
+    """hit_idx rows that are not 16-byte aligned take the scalar copy; same result as aligned rows."""
+    b = synth.generate("realistic", n_events=60, seed=23, with_truth=False)
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    r = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx, b.velo_ty,
+                       b.velo_offsets)
+    res = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(DEV) for k in ("nhits", "hit_idx", "qop", "chi2")}
+    vo = torch.from_numpy(b.velo_offsets.view(np.int32).copy()).to(DEV)
+    n = b.n_tracks
+    buf = torch.zeros(4 * n + 1, dtype=torch.int32, device=DEV)
+    buf[1:] = res["hit_idx"].reshape(-1)
+    shifted = dict(res, hit_idx=buf[1:].view(n, 4))
+    assert shifted["hit_idx"].data_ptr() % 16 == 4
+    g0 = utc.compass_consolidate(b.n_events, vo, res)
+    g1 = utc.compass_consolidate(b.n_events, vo, shifted)
+    torch.cuda.synchronize()
+    nf = int(g0["n_found"].item())
+    assert nf == int(g1["n_found"].item()) and nf > 0
+    for k in ("offsets", "velo", "hit_idx", "nhits", "qop", "chi2"):
+        a, e = g1[k], g0[k]
+        if k != "offsets":
+            a, e = a[:nf], e[:nf]
+        assert torch.equal(a, e), k
