@@ -99,11 +99,23 @@ def _check(status: int, what: str):
         raise RuntimeError(f"{what} failed: {msg} ({status})")
 
 
-def _ptr(t: Optional[torch.Tensor]):
+# element kinds the C ABI expects: (bytes per element, floating point)
+_KINDS = {"i16": (2, False), "i32": (4, False), "f32": (4, True), "f64": (8, True)}
+
+
+def _ptr(t: Optional[torch.Tensor], kind: Optional[str] = None):
+    """Device pointer of a contiguous tensor (None passes NULL); with `kind`, the element width and
+    type are checked, since the library reads raw memory."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    if kind is not None:
+        size, fp = _KINDS[kind]
+        if t.element_size() != size or t.is_floating_point() != fp:
+            raise ValueError(f"{kind} tensor expected, got {t.dtype}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -187,11 +199,12 @@ def ut_decode(geom: Geometry, words, bank_offsets, n_events: int, hit_capacity: 
     out["error_flags"] = error_flags
     if workspace is None:
         workspace = _workspace(L.ut_decode_workspace_bytes(n_events, geom.n_sectors), dev)
-    st = L.ut_decode(geom.ref, _ptr(words), _ptr(bank_offsets), n_events, cap,
-                     _ptr(out["hit_offsets"]), _ptr(out["lhcbid"]), _ptr(out.get("z")), _ptr(out["u"]),
-                     _ptr(out.get("y_begin")), _ptr(out.get("y_end")), _ptr(out["weight"]),
-                     _ptr(error_flags), _ptr(workspace), workspace.numel(), _launch(launch),
-                     _stream(stream))
+    st = L.ut_decode(geom.ref, _ptr(words, "i16"), _ptr(bank_offsets, "i32"), n_events, cap,
+                     _ptr(out["hit_offsets"], "i32"), _ptr(out["lhcbid"], "i32"),
+                     _ptr(out.get("z"), "f32"), _ptr(out["u"], "f32"),
+                     _ptr(out.get("y_begin"), "f32"), _ptr(out.get("y_end"), "f32"),
+                     _ptr(out["weight"], "f32"), _ptr(error_flags, "i32"), _ptr(workspace),
+                     workspace.numel(), _launch(launch), _stream(stream))
     _check(st, "ut_decode")
     return out
 
@@ -218,13 +231,14 @@ def compass_find(geom: Geometry, params, n_events: int, hits, vx, vy, vtx, vty, 
     if workspace is None:
         workspace = _workspace(L.compass_find_workspace_bytes(n_events, n), dev)
     p = params if isinstance(params, UtcCompassParams) else compass_params(params)
-    st = L.compass_find(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"]),
-                        _ptr(hits["u"]), _ptr(hits["weight"]), _ptr(hits.get("y_begin")),
-                        _ptr(hits.get("y_end")), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty),
-                        _ptr(velo_offsets), n, _ptr(out["hit_idx"]), _ptr(out["qop"]),
-                        _ptr(out["chi2"]), _ptr(out["nhits"]), _ptr(out.get("windows")),
-                        _ptr(error_flags), _ptr(workspace), workspace.numel(), _launch(launch),
-                        _stream(stream))
+    st = L.compass_find(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"], "i32"),
+                        _ptr(hits["u"], "f32"), _ptr(hits["weight"], "f32"),
+                        _ptr(hits.get("y_begin"), "f32"), _ptr(hits.get("y_end"), "f32"),
+                        _ptr(vx, "f32"), _ptr(vy, "f32"), _ptr(vtx, "f32"), _ptr(vty, "f32"),
+                        _ptr(velo_offsets, "i32"), n, _ptr(out["hit_idx"], "i32"),
+                        _ptr(out["qop"], "f32"), _ptr(out["chi2"], "f32"), _ptr(out["nhits"], "i32"),
+                        _ptr(out.get("windows"), "i16"), _ptr(error_flags, "i32"), _ptr(workspace),
+                        workspace.numel(), _launch(launch), _stream(stream))
     _check(st, "compass_find")
     return out
 
@@ -246,13 +260,13 @@ def compass_fit_grad(geom: Geometry, track_hit_idx, hit_u, hit_weight, hit_lhcbi
             out["grad_offsets"] = torch.empty(4 * S, dtype=torch.float32, device=dev)
     if workspace is None:
         workspace = _workspace(L.compass_fit_grad_workspace_bytes(S), dev)
-    st = L.compass_fit_grad(geom.ref, n, _ptr(track_hit_idx), int(hit_u.shape[0]), _ptr(hit_u),
-                            _ptr(hit_weight),
-                            _ptr(hit_lhcbid), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty), _ptr(qop),
-                            _ptr(offsets), float(grad_scale), _ptr(out.get("chi2_track")),
-                            _ptr(out.get("chi2_total")), _ptr(out.get("grad_qop")),
-                            _ptr(out.get("grad_offsets")), _ptr(workspace), workspace.numel(),
-                            _stream(stream))
+    st = L.compass_fit_grad(geom.ref, n, _ptr(track_hit_idx, "i32"), int(hit_u.shape[0]),
+                            _ptr(hit_u, "f32"), _ptr(hit_weight, "f32"), _ptr(hit_lhcbid, "i32"),
+                            _ptr(vx, "f32"), _ptr(vy, "f32"), _ptr(vtx, "f32"), _ptr(vty, "f32"),
+                            _ptr(qop, "f32"), _ptr(offsets, "f32"), float(grad_scale),
+                            _ptr(out.get("chi2_track"), "f32"), _ptr(out.get("chi2_total"), "f64"),
+                            _ptr(out.get("grad_qop"), "f32"), _ptr(out.get("grad_offsets"), "f32"),
+                            _ptr(workspace), workspace.numel(), _stream(stream))
     _check(st, "compass_fit_grad")
     return out
 

@@ -91,3 +91,21 @@ def test_nan_states(base):
     vty[3::11] = np.nan
     r, c = _search_both(b, b.detector, d, vel=(vx, b.velo_y, b.velo_tx, vty))
     assert (c["nhits"][::7] == 0).all()
+
+
+def test_binding_rejects_wrong_tensors(base):
+    """The library reads raw memory, so the binding refuses tensors of the wrong element type or
+    layout instead of passing their pointers."""
+    b = base[0]
+    dv = to_dev(b)
+    geom = utc.Geometry(b.detector, DEV)
+    hits = utc.ut_decode(geom, dv["words"], dv["bank_offsets"], b.n_events)
+    vx64 = dv["vel"][0].double()
+    with pytest.raises(ValueError):
+        utc.compass_find(geom, b.params, b.n_events, hits, vx64, *dv["vel"][1:], dv["velo_offsets"])
+    with pytest.raises(ValueError):
+        utc.ut_decode(geom, dv["words"].float(), dv["bank_offsets"], b.n_events)
+    strided = torch.stack([dv["words"], dv["words"]], dim=1)[:, 0]
+    assert not strided.is_contiguous()
+    with pytest.raises(ValueError):
+        utc.ut_decode(geom, strided, dv["bank_offsets"], b.n_events)
