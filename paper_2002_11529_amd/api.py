@@ -414,11 +414,13 @@ def ut_global_event_cut(geom: Geometry, n_events: int, words, bank_offsets, vx, 
     out["error_flags"] = error_flags
     if workspace is None:
         workspace = _workspace(L.ut_global_event_cut_workspace_bytes(n_events), dev)
-    st = L.ut_global_event_cut(geom.ref, n_events, _ptr(words), _ptr(bank_offsets), _ptr(vx), _ptr(vy),
-                               _ptr(vtx), _ptr(vty), _ptr(velo_offsets), int(max_words), _ptr(out["words"]),
-                               _ptr(out["bank_offsets"]), _ptr(out["vx"]), _ptr(out["vy"]), _ptr(out["vtx"]),
-                               _ptr(out["vty"]), _ptr(out["velo_offsets"]), _ptr(out.get("keep")),
-                               _ptr(out.get("n_kept")), _ptr(error_flags), _ptr(workspace),
+    st = L.ut_global_event_cut(geom.ref, n_events, _ptr(words, "i16"), _ptr(bank_offsets, "i32"),
+                               _ptr(vx, "f32"), _ptr(vy, "f32"), _ptr(vtx, "f32"), _ptr(vty, "f32"),
+                               _ptr(velo_offsets, "i32"), int(max_words), _ptr(out["words"], "i16"),
+                               _ptr(out["bank_offsets"], "i32"), _ptr(out["vx"], "f32"),
+                               _ptr(out["vy"], "f32"), _ptr(out["vtx"], "f32"), _ptr(out["vty"], "f32"),
+                               _ptr(out["velo_offsets"], "i32"), _ptr(out.get("keep")),
+                               _ptr(out.get("n_kept"), "i32"), _ptr(error_flags, "i32"), _ptr(workspace),
                                workspace.numel(), _stream(stream))
     _check(st, "ut_global_event_cut")
     return out
@@ -441,10 +443,12 @@ def compass_consolidate(n_events: int, velo_offsets, res, out=None, workspace=No
                    n_found=torch.empty(1, dtype=torch.int32, device=dev))
     if workspace is None:
         workspace = _workspace(L.compass_consolidate_workspace_bytes(n), dev)
-    st = L.compass_consolidate(n_events, _ptr(velo_offsets), n, _ptr(res["nhits"]), _ptr(res["hit_idx"]),
-                               _ptr(res["qop"]), _ptr(res["chi2"]), _ptr(out["offsets"]), _ptr(out["velo"]),
-                               _ptr(out["hit_idx"]), _ptr(out["qop"]), _ptr(out["chi2"]), _ptr(out["nhits"]),
-                               _ptr(out.get("n_found")), _ptr(workspace), workspace.numel(), _stream(stream))
+    st = L.compass_consolidate(n_events, _ptr(velo_offsets, "i32"), n, _ptr(res["nhits"], "i32"),
+                               _ptr(res["hit_idx"], "i32"), _ptr(res["qop"], "f32"), _ptr(res["chi2"], "f32"),
+                               _ptr(out["offsets"], "i32"), _ptr(out["velo"], "i32"),
+                               _ptr(out["hit_idx"], "i32"), _ptr(out["qop"], "f32"), _ptr(out["chi2"], "f32"),
+                               _ptr(out["nhits"], "i32"), _ptr(out.get("n_found"), "i32"), _ptr(workspace),
+                               workspace.numel(), _stream(stream))
     _check(st, "compass_consolidate")
     return out
 
