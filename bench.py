@@ -101,9 +101,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
-    ap.add_argument("--streams", type=int, default=1,
+    ap.add_argument("--streams", type=int, default=0,
                     help="consecutive steps go to this many streams in turn (independent batches in flight "
-                         "at once); every buffer copy stays on one stream")
+                         "at once); every buffer copy stays on one stream.  0: each of 1, 2 and 3 streams "
+                         "is timed over a short burst first and the fastest is used")
     ap.add_argument("--no-copy-bandwidth", action="store_true",
                     help="skip the 1 GiB device copy that measures the card's streaming bandwidth")
     ap.add_argument("--no-compact", action="store_true",
@@ -146,8 +147,9 @@ def main():
     params = utc.compass_params(b.params)
     L = utc.library()
 
-    NS = max(1, args.streams)
-    R = -(-max(1, args.rotate, NS) // NS) * NS   # a multiple of the stream count
+    NS_CHOICES = (1, 2, 3) if args.streams <= 0 else (args.streams,)
+    LCM = int(np.lcm.reduce(NS_CHOICES))
+    R = -(-max(1, args.rotate, LCM) // LCM) * LCM   # a multiple of every stream count tried
     copies = []
     for _ in range(R):
         words = torch.from_numpy(b.words.view(np.int16).copy()).to(dev)
@@ -242,27 +244,41 @@ def main():
             graphs[i % R].replay()
         torch.cuda.synchronize()
 
-    # timed region: K whole steps, bracketed by synchronisation; step i runs on stream i % NS
-    streams = [stream] + [torch.cuda.Stream() for _ in range(NS - 1)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for st in streams[1:]:
-        st.wait_stream(stream)
-    for i in range(K):
-        with torch.cuda.stream(streams[i % NS]):
-            if graphs is not None:
-                graphs[i % R].replay()
-            else:
-                step(copies[i % R])
-    for st in streams[1:]:
-        stream.wait_stream(st)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = t_start.elapsed_time(t_end)
+    # K whole steps, bracketed by synchronisation; step i runs on stream i % ns
+    side_streams = [torch.cuda.Stream() for _ in range(max(NS_CHOICES) - 1)]
+
+    def run_steps(ns, k):
+        streams = [stream] + side_streams[:ns - 1]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t_start.record(stream)
+        for st in streams[1:]:
+            st.wait_stream(stream)
+        for i in range(k):
+            with torch.cuda.stream(streams[i % ns]):
+                if graphs is not None:
+                    graphs[i % R].replay()
+                else:
+                    step(copies[i % R])
+        for st in streams[1:]:
+            stream.wait_stream(st)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end), time.perf_counter() - wall0
+
+    # the stream count: the fastest of the candidates over short bursts (twice each, best kept)
+    stream_trials = None
+    NS = NS_CHOICES[0]
+    if len(NS_CHOICES) > 1:
+        kt = max(2 * LCM, K // 2)
+        stream_trials = {ns: min(run_steps(ns, kt)[0] for _ in range(2)) / kt for ns in NS_CHOICES}
+        NS = min(stream_trials, key=stream_trials.get)
+        stream_trials = {str(ns): round(ms, 5) for ns, ms in stream_trials.items()}
+
+    # timed region
+    ms_total, wall = run_steps(NS, K)
     ms_per_step = ms_total / K
     if int(flags.item()) != 0:
         raise RuntimeError(f"device error flags {int(flags.item())}")
@@ -349,7 +365,8 @@ def main():
         "config": {"workload": f"{args.workload}: {E} events, {S} sectors/layer, {Nt} VELO tracks, "
                                f"{Nh} hits, {Nw} raw words",
                    "step": "ut_decode + compass_find + compass_fit_grad(fwd+bwd)",
-                   "rotated_copies": R, "streams": NS},
+                   "rotated_copies": R, "streams": NS,
+                   "stream_trials_ms_per_step": stream_trials},
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
