@@ -30,8 +30,9 @@ __device__ inline double from_fixed(uint64_t hi, uint64_t lo) {
 
 // Per-workgroup partial sums: workgroup b writes column b of part[2*(4S+1)][grid], the (hi, lo)
 // pairs of the 4S sector sums and, last, of the total chi2.  The sums are accumulated in LDS when
-// they fit (lds_acc), else with integer atomics directly in the workgroup's own column, cleared
+// they fit (kLdsAcc), else with integer atomics directly in the workgroup's own column, cleared
 // beforehand by k_fitgrad_clear; either way a workgroup writes its own column and nothing else.
+template <bool kLdsAcc>
 __global__ void __launch_bounds__(1024)
 k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, int64_t n_hits,
           const float* __restrict__ hu, const float* __restrict__ hw,
@@ -39,17 +40,17 @@ k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, i
           const float* __restrict__ vy, const float* __restrict__ vtx,
           const float* __restrict__ vty, const float* __restrict__ qop,
           const float* __restrict__ offsets, float m2s, float* __restrict__ chi2_track,
-          float* __restrict__ grad_qop, bool want_sums, bool lds_acc, uint64_t* __restrict__ part)
+          float* __restrict__ grad_qop, bool want_sums, uint64_t* __restrict__ part)
 {
-  extern __shared__ uint64_t s_acc[];  // [2 * (4S + 1)] when want_sums and lds_acc
+  extern __shared__ uint64_t s_acc[];  // [2 * (4S + 1)] when want_sums and kLdsAcc
   const int S = g.S;
   const int n_sums = kLayers * S + 1;
   uint64_t* col = part + blockIdx.x;   // this workgroup's column, stride gridDim.x
   auto acc_add = [&](int i, uint64_t v) {
-    if (lds_acc) atomicAdd((unsigned long long*)&s_acc[i], (unsigned long long)v);
+    if constexpr (kLdsAcc) atomicAdd((unsigned long long*)&s_acc[i], (unsigned long long)v);
     else atomicAdd((unsigned long long*)&col[(size_t)i * gridDim.x], (unsigned long long)v);
   };
-  if (want_sums && lds_acc) {
+  if (kLdsAcc && want_sums) {
     for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x) s_acc[i] = 0;
     __syncthreads();
   }
@@ -104,7 +105,7 @@ k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, i
     acc_add(2 * (n_sums - 1), tot_hi);
     acc_add(2 * (n_sums - 1) + 1, tot_lo);
   }
-  if (!lds_acc) return;
+  if constexpr (!kLdsAcc) return;
   __syncthreads();
   // column blockIdx.x of the sum-major partial array part[2*n_sums][gridDim.x]
   for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x)
@@ -189,15 +190,20 @@ extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_track
   int64_t blocks = (n_tracks + block - 1) / block;
   if (blocks > kMaxRows) blocks = kMaxRows;
   if (blocks < 1) blocks = 1;
-  if (!allow_dynamic_lds(reinterpret_cast<const void*>(k_fitgrad), lds)) return UTC_ERR_HIP;
+  if (lds_acc && !allow_dynamic_lds(reinterpret_cast<const void*>(k_fitgrad<true>), lds)) return UTC_ERR_HIP;
   if (want_sums && !lds_acc) {
     const int64_t n = 2 * (int64_t)n_sums * blocks;
     hipLaunchKernelGGL(k_fitgrad_clear, dim3((unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096)),
                        dim3(256), 0, stream, part, n);
   }
-  hipLaunchKernelGGL(k_fitgrad, dim3((unsigned)blocks), dim3(block), lds, stream, g, n_tracks,
-                     track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop,
-                     offsets, m2s, chi2_track, grad_qop, want_sums, lds_acc, part);
+  if (lds_acc)
+    hipLaunchKernelGGL(k_fitgrad<true>, dim3((unsigned)blocks), dim3(block), lds, stream, g, n_tracks,
+                       track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop,
+                       offsets, m2s, chi2_track, grad_qop, want_sums, part);
+  else
+    hipLaunchKernelGGL(k_fitgrad<false>, dim3((unsigned)blocks), dim3(block), 0, stream, g, n_tracks,
+                       track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop,
+                       offsets, m2s, chi2_track, grad_qop, want_sums, part);
   if (want_sums)
     hipLaunchKernelGGL(k_fitgrad_finalize, dim3((n_sums + 3) / 4), dim3(256), 0, stream, part,
                        (int)blocks, n_sums, -2.0 * (double)grad_scale, grad_offsets, chi2_total);
