@@ -51,9 +51,23 @@ def kernel_source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def counter_fields(kernel, workload, what):
+def launch_tag(launch, n_items=None, items_per_workgroup=1):
+    """The launch shape as the counter summaries record it.  A persistent grid with a workgroup
+    for every work item maps the work exactly as one workgroup per item does, so both have one
+    tag."""
+    if not launch:
+        return "defaults"
+    g = launch["grid"]
+    if g == 0 or (n_items is not None and g * items_per_workgroup >= n_items):
+        g = "per-item"
+    return f"block={launch['block']} grid={g}"
+
+
+def counter_fields(kernel, workload, what, launch=None):
     """Fields of the committed counter summary profiles/{workload}_{what}_counters.txt, or None
-    when there is none or it was taken from other kernel sources than the current ones."""
+    when there is none, or it was taken from other kernel sources than the current ones, or (for
+    an autotuned kernel) at another launch shape (`launch`, a launch_tag): a kernel's cache
+    behaviour, and so its HBM traffic, depends on how many events are in flight at once."""
     path = os.path.join(ROOT, "profiles", f"{workload}_{what}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -65,22 +79,24 @@ def counter_fields(kernel, workload, what):
                 fields[k.strip()] = v.strip()
     if fields.get(f"{kernel}.source_sha256_16") != kernel_source_hash(kernel):
         return None
+    if f"{kernel}.launch" in fields and fields[f"{kernel}.launch"] != launch:
+        return None
     return fields
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, launch=None):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a
-    plain copy of known size), or None (no summary, or one of other kernel sources)."""
-    fields = counter_fields(kernel, workload, "hbm")
+    plain copy of known size), or None (no summary, or one of other kernel sources or shape)."""
+    fields = counter_fields(kernel, workload, "hbm", launch)
     try:
         return int(fields[f"{kernel}.hbm_bytes_per_launch"]) if fields else None
     except (KeyError, ValueError):
         return None
 
 
-def measured_valu(kernel, workload):
+def measured_valu(kernel, workload, launch=None):
     """Vector-ALU instructions (wave64) per launch of `kernel` (SQ_INSTS_VALU), or None."""
-    fields = counter_fields(kernel, workload, "sq")
+    fields = counter_fields(kernel, workload, "sq", launch)
     try:
         return int(fields[f"{kernel}.valu_instr_per_launch"]) if fields else None
     except (KeyError, ValueError):
@@ -345,6 +361,9 @@ def main():
     names = ["ut_decode", "compass_find", "compass_fit_grad"]
     per_call_bytes = [bytes_decode, bytes_find, bytes_fg]
     dom = int(np.argmax(call_ms))
+    shape_tags = {"k_decode": launch_tag(lau_dec, 4 * E, (lau_dec or {}).get("block", 64) // 64),
+                  "k_compass": launch_tag(lau_find, E)}
+    lau_dom = shape_tags.get(KERNEL_OF_CALL[names[dom]])
     achieved = per_call_bytes[dom] / (call_ms[dom] * 1e-3) / 1e9
     value = E / (ms_per_step * 1e-3)
     copy_bw = None if args.no_copy_bandwidth else copy_bandwidth()
@@ -370,15 +389,17 @@ def main():
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload),
+                     "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload, lau_dom),
                      "copy_GBps": round(copy_bw, 1) if copy_bw else None,
                      "frac_of_copy": round(achieved / copy_bw, 4) if copy_bw else None,
-                     "valu_issue": valu_issue(KERNEL_OF_CALL[names[dom]], args.workload, call_ms[dom])},
+                     "valu_issue": valu_issue(KERNEL_OF_CALL[names[dom]], args.workload, call_ms[dom],
+                                              lau_dom)},
         "calls_ms": {n: round(float(m), 5) for n, m in zip(names, call_ms)},
         "step_algorithmic_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "decode_GBps": round(bytes_decode / (call_ms[0] * 1e-3) / 1e9, 1),
         "timing": "hip graph replay" if graphs is not None else "eager launches",
-        "launch": {"decode": lau_dec, "find": lau_find, "source": "autotuner" if tuned else "defaults"},
+        "launch": {"decode": lau_dec, "find": lau_find, "source": "autotuner" if tuned else "defaults",
+                   "shape_tags": shape_tags},
         "batched_vs_per_event": per_event,
         "compact_hits": compact,
         "found_fraction": round(n_found / max(Nt, 1), 5),
@@ -491,10 +512,10 @@ def copy_calibration():
     print(json.dumps({"copy_calibration_bytes_read": n, "bytes_written": n, "copies": 5}), flush=True)
 
 
-def valu_issue(kernel, workload, ms):
+def valu_issue(kernel, workload, ms, launch=None):
     """The kernel's measured vector-instruction rate against the VALU issue ceiling, the bound the
     search and decode kernels actually run into (None without a current counter summary)."""
-    n = measured_valu(kernel, workload)
+    n = measured_valu(kernel, workload, launch)
     if n is None:
         return None
     rate = n / (ms * 1e-3)

@@ -172,8 +172,10 @@ utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks, const in
  * and meaning as ut_decode / compass_find) for every candidate launch shape: block in
  * {64, 128, 256, 512} (decode and Compass), grid in {one workgroup per work
  * item, 256 .. 2048 persistent workgroups}; each shape runs once to warm up and then `reps` times
- * (1..32).  *best receives the shape with the lowest median time, *best_us that time in
- * microseconds.  Results do not depend on the shape.  Unlike the other calls these synchronise
+ * (1..32).  *best receives the first shape, in the order block then grid of the lists above,
+ * whose median time is within 2 % of the lowest median (near-equal shapes are within the timing
+ * noise; the rule keeps repeated tunings on one shape), *best_us its median in microseconds.
+ * Results do not depend on the shape.  Unlike the other calls these synchronise
  * the stream (set-up calls); the outputs hold the last run's results.
  * --------------------------------------------------------------------------------------------- */
 utc_status ut_decode_autotune(const utc_geometry* geom, const uint16_t* words,

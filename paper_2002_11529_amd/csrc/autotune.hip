@@ -1,6 +1,8 @@
 // Launch-shape autotuner for the batched path: times candidate (block, grid) shapes of ut_decode
-// and compass_find on the caller's own buffers with HIP events and keeps the fastest.  A set-up
-// call: it synchronises the stream, unlike the other entry points.
+// and compass_find on the caller's own buffers with HIP events and keeps the first candidate, in
+// the listed order, within kTieFrac of the fastest (near-equal shapes are within the timing noise;
+// the rule keeps the choice from flipping between them from run to run).  A set-up call: it
+// synchronises the stream, unlike the other entry points.
 #include "common.hpp"
 
 namespace {
@@ -39,6 +41,34 @@ float median_us(F&& run, int reps, hipStream_t stream, Timer& tm, bool& ok) {
   return best[n / 2];
 }
 
+constexpr float kTieFrac = 0.02f;
+
+// Times every (block, grid) of the two lists with run(config) and picks as described above.
+template <class F>
+utc_status tune_shapes(const int* blocks, int nb, const int* grids, int ng, F&& run, int reps,
+                       hipStream_t stream, utc_launch_config* best, float* best_us) {
+  Timer tm;
+  float t[64];
+  bool okc[64];
+  float t_min = 3.0e38f;
+  for (int i = 0; i < nb; ++i)
+    for (int j = 0; j < ng; ++j) {
+      utc_launch_config c{blocks[i], grids[j], 0, 0};
+      bool ok = false;
+      const int k = i * ng + j;
+      t[k] = median_us([&] { return run(&c); }, reps, stream, tm, ok);
+      okc[k] = ok;
+      if (ok && t[k] < t_min) t_min = t[k];
+    }
+  for (int k = 0; k < nb * ng; ++k)
+    if (okc[k] && t[k] <= t_min * (1.0f + kTieFrac)) {
+      *best = utc_launch_config{blocks[k / ng], grids[k % ng], 0, 0};
+      *best_us = t[k];
+      return UTC_OK;
+    }
+  return UTC_ERR_ARG;
+}
+
 }  // namespace
 
 extern "C" utc_status ut_decode_autotune(const utc_geometry* geom, const uint16_t* words,
@@ -53,27 +83,10 @@ extern "C" utc_status ut_decode_autotune(const utc_geometry* geom, const uint16_
   if (!best || !best_us) return UTC_ERR_ARG;
   static const int blocks[] = {64, 128, 256, 512};
   static const int grids[] = {0, 256, 512, 1024, 2048};
-  Timer tm;
-  float t_best = 3.0e38f;
-  bool any = false;
-  for (int b : blocks)
-    for (int gsz : grids) {
-      utc_launch_config c{b, gsz, 0, 0};
-      bool ok = false;
-      const float t = median_us([&] {
-        return ut_decode(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, z,
-                         u, y_begin, y_end, weight, error_flags, workspace, workspace_bytes, &c,
-                         stream);
-      }, reps, stream, tm, ok);
-      if (ok && t < t_best) {
-        t_best = t;
-        *best = c;
-        any = true;
-      }
-    }
-  if (!any) return UTC_ERR_ARG;
-  *best_us = t_best;
-  return UTC_OK;
+  return tune_shapes(blocks, 4, grids, 5, [&](const utc_launch_config* c) {
+    return ut_decode(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, z, u,
+                     y_begin, y_end, weight, error_flags, workspace, workspace_bytes, c, stream);
+  }, reps, stream, best, best_us);
 }
 
 extern "C" utc_status compass_find_autotune(const utc_geometry* geom, const utc_compass_params* params,
@@ -91,25 +104,9 @@ extern "C" utc_status compass_find_autotune(const utc_geometry* geom, const utc_
   if (!best || !best_us) return UTC_ERR_ARG;
   static const int blocks[] = {64, 128, 256, 512};
   static const int grids[] = {0, 512, 1024, 2048};
-  Timer tm;
-  float t_best = 3.0e38f;
-  bool any = false;
-  for (int b : blocks)
-    for (int gsz : grids) {
-      utc_launch_config c{b, gsz, 0, 0};
-      bool ok = false;
-      const float t = median_us([&] {
-        return compass_find(geom, params, n_events, hit_offsets, hit_u, hit_weight, hit_y_begin,
-                            hit_y_end, vx, vy, vtx, vty, velo_offsets, n_tracks, hit_idx, qop, chi2,
-                            nhits, nullptr, error_flags, workspace, workspace_bytes, &c, stream);
-      }, reps, stream, tm, ok);
-      if (ok && t < t_best) {
-        t_best = t;
-        *best = c;
-        any = true;
-      }
-    }
-  if (!any) return UTC_ERR_ARG;
-  *best_us = t_best;
-  return UTC_OK;
+  return tune_shapes(blocks, 4, grids, 4, [&](const utc_launch_config* c) {
+    return compass_find(geom, params, n_events, hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end,
+                        vx, vy, vtx, vty, velo_offsets, n_tracks, hit_idx, qop, chi2, nhits, nullptr,
+                        error_flags, workspace, workspace_bytes, c, stream);
+  }, reps, stream, best, best_us);
 }
