@@ -362,10 +362,11 @@ def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy,
     hits = ut_decode(geom, words, bank_offsets, n_events, stream=stream)
     ws = _workspace(L.ut_decode_workspace_bytes(n_events, geom.n_sectors), dev)
     best, best_us = UtcLaunchConfig(), ctypes.c_float()
-    st = L.ut_decode_autotune(geom.ref, _ptr(words), _ptr(bank_offsets), n_events,
-                              int(words.shape[0]), _ptr(hits["hit_offsets"]), _ptr(hits["lhcbid"]),
-                              _ptr(hits["z"]), _ptr(hits["u"]), _ptr(hits["y_begin"]),
-                              _ptr(hits["y_end"]), _ptr(hits["weight"]), _ptr(hits["error_flags"]),
+    st = L.ut_decode_autotune(geom.ref, _ptr(words, "i16"), _ptr(bank_offsets, "i32"), n_events,
+                              int(words.shape[0]), _ptr(hits["hit_offsets"], "i32"),
+                              _ptr(hits["lhcbid"], "i32"), _ptr(hits["z"], "f32"), _ptr(hits["u"], "f32"),
+                              _ptr(hits["y_begin"], "f32"), _ptr(hits["y_end"], "f32"),
+                              _ptr(hits["weight"], "f32"), _ptr(hits["error_flags"], "i32"),
                               _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(best_us),
                               _stream(stream))
     _check(st, "ut_decode_autotune")
@@ -373,11 +374,13 @@ def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy,
     dec_us = float(best_us.value)
     res = compass_find(geom, p, n_events, hits, vx, vy, vtx, vty, velo_offsets, stream=stream)
     wsf = _workspace(L.compass_find_workspace_bytes(n_events, n_tracks), dev)
-    st = L.compass_find_autotune(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"]),
-                                 _ptr(hits["u"]), _ptr(hits["weight"]), _ptr(hits["y_begin"]),
-                                 _ptr(hits["y_end"]), _ptr(vx), _ptr(vy), _ptr(vtx), _ptr(vty),
-                                 _ptr(velo_offsets), n_tracks, _ptr(res["hit_idx"]), _ptr(res["qop"]),
-                                 _ptr(res["chi2"]), _ptr(res["nhits"]), _ptr(res["error_flags"]),
+    st = L.compass_find_autotune(geom.ref, ctypes.byref(p), n_events, _ptr(hits["hit_offsets"], "i32"),
+                                 _ptr(hits["u"], "f32"), _ptr(hits["weight"], "f32"),
+                                 _ptr(hits["y_begin"], "f32"), _ptr(hits["y_end"], "f32"),
+                                 _ptr(vx, "f32"), _ptr(vy, "f32"), _ptr(vtx, "f32"), _ptr(vty, "f32"),
+                                 _ptr(velo_offsets, "i32"), n_tracks, _ptr(res["hit_idx"], "i32"),
+                                 _ptr(res["qop"], "f32"), _ptr(res["chi2"], "f32"), _ptr(res["nhits"], "i32"),
+                                 _ptr(res["error_flags"], "i32"),
                                  _ptr(wsf), wsf.numel(), reps, ctypes.byref(best),
                                  ctypes.byref(best_us), _stream(stream))
     _check(st, "compass_find_autotune")
