@@ -12,6 +12,14 @@ namespace utc {
 
 // kGreedy: the paper's search variant (max_tracklets > 0), a kernel of its own so that its code
 // does not weigh on the register allocation of the default search
+// The next group of tracks for the calling wave: groups are handed out in order from a counter in
+// LDS, so the waves of a workgroup finish an event together whatever each group costs.
+__device__ inline uint32_t claim_group(uint32_t* counter) {
+  uint32_t v = 0;
+  if (lane_id() == 0) v = atomicAdd(counter, 1u);
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);   // every lane is active here
+}
+
 template <bool kGreedy>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
@@ -26,6 +34,7 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
   const int wid = tid / kWave, nwaves = bs / kWave;
   uint32_t* s_hoff = reinterpret_cast<uint32_t*>(smem);
   float* s_u = reinterpret_cast<float*>(s_hoff + ((nb + 1 + 3) & ~3));
+  uint32_t* s_next = s_hoff + nb + 1;   // group counter, in the padding after the offsets
   char* gbase = reinterpret_cast<char*>(s_u + u_cap);
   const GroupScratch gs = carve_group(gbase + (size_t)wid * group_scratch_bytes(p.max_hits), p.max_hits);
 
@@ -45,6 +54,7 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
         if (j <= nb) s_hoff[j] = v[q] - H;
       }
     }
+    if (tid == 0) *s_next = (uint32_t)nwaves;   // groups 0 .. nwaves-1 go to the waves in order
     __syncthreads();
     const uint32_t nh = s_hoff[nb];
     bool overflow = false;
@@ -85,19 +95,26 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     ev.stride = staged ? 1u : (ncoarse > 0 ? stride : 0u);
     const uint32_t t0 = velo_offsets[e], t1 = velo_offsets[e + 1];
     const uint32_t ngroups = (t1 - t0 + kGroupTracks - 1) / kGroupTracks;
-    // the next group's VELO states are loaded while the current group is searched
-    LaneState st = load_state(io, t0 + wid * kGroupTracks, t1);
+    // a wave claims its next group before searching the current one, so that the next group's
+    // VELO states are loaded meanwhile
+    uint32_t grp = (uint32_t)wid;
+    uint32_t nxt = grp < ngroups ? claim_group(s_next) : ngroups;
+    LaneState st = load_state(io, t0 + grp * kGroupTracks, t1);
     if (staged) {
-      for (uint32_t grp = wid; grp < ngroups; grp += nwaves) {
-        const LaneState next = load_state(io, t0 + (grp + nwaves) * kGroupTracks, t1);
+      while (grp < ngroups) {
+        const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
         compass_group<true, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
         st = next;
+        grp = nxt;
+        nxt = grp < ngroups ? claim_group(s_next) : ngroups;
       }
     } else {
-      for (uint32_t grp = wid; grp < ngroups; grp += nwaves) {
-        const LaneState next = load_state(io, t0 + (grp + nwaves) * kGroupTracks, t1);
+      while (grp < ngroups) {
+        const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
         compass_group<false, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
         st = next;
+        grp = nxt;
+        nxt = grp < ngroups ? claim_group(s_next) : ngroups;
       }
     }
     __syncthreads();
