@@ -125,7 +125,9 @@ utc_status ut_decode(const utc_geometry* geom, const uint16_t* words, const uint
  * [4t + l] = (first hit - first hit of its (event, layer), size), (-1, 0) when not searched.
  * hit_y_begin and hit_y_end may both be NULL: every strip then spans the geometry's
  * [y_begin, y_end] (what ut_decode writes; the compact form of the hits).
- * Workspace: compass_find_workspace_bytes() bytes, any content.
+ * Workspace: compass_find_workspace_bytes() bytes, any content.  A persistent launch (grid > 0 and
+ * fewer workgroups than events) keeps its event counter there (reset by the call, on the stream):
+ * calls in flight at the same time need workspaces of their own.
  * --------------------------------------------------------------------------------------------- */
 size_t compass_find_workspace_bytes(int32_t n_events, int64_t n_tracks);
 

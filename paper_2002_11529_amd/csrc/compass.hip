@@ -25,7 +25,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets,
           const float* __restrict__ hu, const float* __restrict__ hw,
           const float* __restrict__ hyb, const float* __restrict__ hye,
-          const uint32_t* __restrict__ velo_offsets, TrackIO io, uint32_t* flags, int u_cap)
+          const uint32_t* __restrict__ velo_offsets, TrackIO io, uint32_t* flags, int u_cap,
+          uint32_t* ev_counter)
 {
   extern __shared__ __align__(16) char smem[];
   const int S = g.S;
@@ -35,10 +36,14 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
   uint32_t* s_hoff = reinterpret_cast<uint32_t*>(smem);
   float* s_u = reinterpret_cast<float*>(s_hoff + ((nb + 1 + 3) & ~3));
   uint32_t* s_next = s_hoff + nb + 1;   // group counter, in the padding after the offsets
+  uint32_t* s_event = s_hoff + nb + 2;  // the workgroup's next event (persistent grids)
   char* gbase = reinterpret_cast<char*>(s_u + u_cap);
   const GroupScratch gs = carve_group(gbase + (size_t)wid * group_scratch_bytes(p.max_hits), p.max_hits);
 
-  for (int e = blockIdx.x; e < n_events; e += gridDim.x) {
+  // a persistent grid (ev_counter set, cleared to gridDim.x beforehand) takes events 0..grid-1 in
+  // order and then claims the next event whenever a workgroup finishes one, so uneven events
+  // spread over the workgroups as they free up; otherwise one workgroup per event
+  for (int e = blockIdx.x; e < n_events;) {
     const int64_t eb = (int64_t)e * nb;
     const uint32_t H = hit_offsets[eb];
     for (int j0 = 0; j0 <= nb; j0 += 4 * bs) {
@@ -118,7 +123,19 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
       }
     }
     __syncthreads();
+    if (ev_counter) {
+      if (tid == 0) *s_event = atomicAdd(ev_counter, 1u);
+      __syncthreads();
+      e = (int)min(*s_event, (uint32_t)n_events);
+    } else {
+      e += gridDim.x;
+    }
   }
+}
+
+// Sets the event counter of a persistent launch to its grid size.
+__global__ void k_compass_start(uint32_t* ev_counter, uint32_t grid) {
+  if (threadIdx.x == 0) *ev_counter = grid;
 }
 
 size_t compass_lds_bytes(int S, int max_hits, int waves, int u_cap) {
@@ -192,17 +209,21 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   if (lds > 160 * 1024) return UTC_ERR_ARG;
   (void)hipGetLastError();  // report only errors of this call
   const int grid = (launch && launch->grid > 0) ? launch->grid : n_events;
+  // persistent launches hand out events from a counter in the workspace
+  uint32_t* ev_counter = grid < n_events ? static_cast<uint32_t*>(workspace) : nullptr;
   TrackIO io{vx, vy, vtx, vty, hit_idx, qop, chi2, nhits, windows};
   const void* kern = p.max_tracklets > 0 ? reinterpret_cast<const void*>(k_compass<true>)
                                           : reinterpret_cast<const void*>(k_compass<false>);
   if (!allow_dynamic_lds(kern, lds)) return UTC_ERR_HIP;
+  if (ev_counter)
+    hipLaunchKernelGGL(k_compass_start, dim3(1), dim3(64), 0, stream, ev_counter, (uint32_t)grid);
   if (p.max_tracklets > 0)
     hipLaunchKernelGGL(k_compass<true>, dim3(grid), dim3(block), lds, stream, g, p, n_events,
                        hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end, velo_offsets, io,
-                       error_flags, u_cap);
+                       error_flags, u_cap, ev_counter);
   else
     hipLaunchKernelGGL(k_compass<false>, dim3(grid), dim3(block), lds, stream, g, p, n_events,
                        hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end, velo_offsets, io,
-                       error_flags, u_cap);
+                       error_flags, u_cap, ev_counter);
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
 }
