@@ -203,7 +203,7 @@ def main():
     lau_dec = tuned["decode"] if tuned else None
     lau_find = tuned["find"] if tuned else None
 
-    def step(c, ev=None, compact=False):
+    def step(c, ev=None, compact=False, lf=lau_find):
         stream = torch.cuda.current_stream()
         # the compact form passes no z / y_begin / y_end: the decoder skips those stores and the
         # search takes the detector's y range for every strip
@@ -215,7 +215,7 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         utc.compass_find(geom, params, E, hits, *c["vel"], c["vo"], error_flags=flags,
-                         out=c["res"], workspace=c["ws"]["find"], launch=lau_find)
+                         out=c["res"], workspace=c["ws"]["find"], launch=lf)
         if ev is not None:
             ev[2].record(stream)
         utc.compass_fit_grad(geom, c["res"]["hit_idx"], hits["u"], hits["weight"],
@@ -241,29 +241,41 @@ def main():
     torch.cuda.synchronize()
     call_ms = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs]).mean(axis=0)
 
-    # the step captured once per buffer copy in a HIP graph, replayed
-    graphs = None
+    # the search's launch shapes tried with the stream counts: the tuned one (timed on one stream)
+    # and, when that is a persistent grid, one workgroup per event, whose uneven tails leave room
+    # for the steps on other streams
+    find_choices = [lau_find]
+    if lau_find and 0 < lau_find["grid"] < E:
+        find_choices.append({"block": 256, "grid": 0})
+
+    # the step captured once per buffer copy (and search shape) in a HIP graph, replayed
+    graph_sets = None
     if not args.no_graph:
-        graphs = []
+        graph_sets = []
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            for c in copies:
-                gph = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(gph, stream=side):
-                    stream = torch.cuda.current_stream()
-                    step(c)
-                graphs.append(gph)
+            for lf in find_choices:
+                gs = []
+                for c in copies:
+                    gph = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(gph, stream=side):
+                        stream = torch.cuda.current_stream()
+                        step(c, lf=lf)
+                    gs.append(gph)
+                graph_sets.append(gs)
         torch.cuda.current_stream().wait_stream(side)
         stream = torch.cuda.current_stream()
-        for i in range(args.warmup):
-            graphs[i % R].replay()
+        for gs in graph_sets:
+            for i in range(args.warmup):
+                gs[i % R].replay()
         torch.cuda.synchronize()
+    graphs = graph_sets[0] if graph_sets else None
 
     # K whole steps, bracketed by synchronisation; step i runs on stream i % ns
     side_streams = [torch.cuda.Stream() for _ in range(max(NS_CHOICES) - 1)]
 
-    def run_steps(ns, k):
+    def run_steps(ns, k, gi=0):
         streams = [stream] + side_streams[:ns - 1]
         t_start = torch.cuda.Event(enable_timing=True)
         t_end = torch.cuda.Event(enable_timing=True)
@@ -274,30 +286,34 @@ def main():
             st.wait_stream(stream)
         for i in range(k):
             with torch.cuda.stream(streams[i % ns]):
-                if graphs is not None:
-                    graphs[i % R].replay()
+                if graph_sets is not None:
+                    graph_sets[gi][i % R].replay()
                 else:
-                    step(copies[i % R])
+                    step(copies[i % R], lf=find_choices[gi])
         for st in streams[1:]:
             stream.wait_stream(st)
         t_end.record(stream)
         torch.cuda.synchronize()
         return t_start.elapsed_time(t_end), time.perf_counter() - wall0
 
-    # the stream count: the fastest of the candidates over short bursts (twice each, best kept)
+    # the stream count (and search shape): the fastest of the candidates over short bursts (twice
+    # each, best kept)
     stream_trials = None
-    NS = NS_CHOICES[0]
-    if len(NS_CHOICES) > 1:
+    NS, GI = NS_CHOICES[0], 0
+    if len(NS_CHOICES) > 1 or len(find_choices) > 1:
         kt = max(2 * LCM, min(K // 2, 60))
-        stream_trials = {ns: min(run_steps(ns, kt)[0] for _ in range(2)) / kt for ns in NS_CHOICES}
-        NS = min(stream_trials, key=stream_trials.get)
-        stream_trials = {str(ns): round(ms, 5) for ns, ms in stream_trials.items()}
+        trials = {(ns, gi): min(run_steps(ns, kt, gi)[0] for _ in range(2)) / kt
+                  for gi in range(len(find_choices)) for ns in NS_CHOICES}
+        NS, GI = min(trials, key=trials.get)
+        name = (lambda ns, gi: str(ns)) if len(find_choices) == 1 else \
+               (lambda ns, gi: f"{ns} streams, search {launch_tag(find_choices[gi], E)}")
+        stream_trials = {name(ns, gi): round(ms, 5) for (ns, gi), ms in trials.items()}
 
     # the streams' first use costs milliseconds once: a warm-up pass on the chosen streams (the
     # trials above already made one), then the timed region
     if stream_trials is None:
         run_steps(NS, max(2 * R, args.warmup))
-    ms_total, wall = run_steps(NS, K)
+    ms_total, wall = run_steps(NS, K, GI)
     ms_per_step = ms_total / K
     if int(flags.item()) != 0:
         raise RuntimeError(f"device error flags {int(flags.item())}")
@@ -387,7 +403,7 @@ def main():
         "config": {"workload": f"{args.workload}: {E} events, {S} sectors/layer, {Nt} VELO tracks, "
                                f"{Nh} hits, {Nw} raw words",
                    "step": "ut_decode + compass_find + compass_fit_grad(fwd+bwd)",
-                   "rotated_copies": R, "streams": NS,
+                   "rotated_copies": R, "streams": NS, "search_launch_timed": find_choices[GI],
                    "stream_trials_ms_per_step": stream_trials},
         "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
