@@ -115,12 +115,17 @@ static int in_acceptance(const ora_detector* det, const ora_extrap* x)
   return 1;
 }
 
-/* Window of one layer (Section V-A): the sector the prediction points to and its neighbours
-   (1, 3 or 5 sectors, fewer at the layer edges), the hits with u in [up - W, up + W], cut to the
-   max_hits hits nearest to the prediction.  Linear scans stand in for the paper's binary searches. */
+/* Window of one layer (Section V-A): the sector the prediction points to (the central sector c) and
+   its neighbours (1, 3 or 5 sectors, fewer at the layer edges), the hits with u in [up - W, up + W],
+   cut to the max_hits hits nearest to the prediction.  Linear scans stand in for the paper's binary
+   searches. */
+typedef struct {
+  int64_t first, end;     /* window hits [first, end), global indices, ascending x */
+  int32_t c, s_lo, s_hi;  /* central sector and the allowed sector range */
+} ora_window;
+
 static void find_window(const ora_detector* det, const ora_params* par, const uint32_t* hit_offsets,
-                        const float* hit_u, int64_t layer_bank0, float up, float W,
-                        int64_t* first_out, int64_t* end_out)
+                        const float* hit_u, int64_t layer_bank0, float up, float W, ora_window* win)
 {
   const int32_t S = det->n_sectors;
   const int32_t half = (par->n_sectors_search - 1) / 2;
@@ -141,8 +146,34 @@ static void find_window(const ora_detector* det, const ora_params* par, const ui
     float dr = hit_u[end - 1] - up;
     if (dr >= dl) --end; else ++first;
   }
-  *first_out = first;
-  *end_out = end;
+  win->first = first;
+  win->end = end;
+  win->c = c;
+  win->s_lo = s_lo;
+  win->s_hi = s_hi;
+}
+
+/* The hits of a window in the order the paper's search walks its combined ranges (Section V-B): the
+   central sector first, then its immediate neighbours, the extreme sectors of a five-sector search
+   last; of two neighbours at the same distance the left one (lower sector) first; ascending x
+   inside a sector.  Returns the number of hits written to out. */
+static int walk_order(const ora_params* par, const uint32_t* hit_offsets, int64_t layer_bank0,
+                      const ora_window* win, int64_t* out)
+{
+  const int32_t half = (par->n_sectors_search - 1) / 2;
+  int n = 0;
+  for (int32_t k = 0; k <= half; ++k) {
+    for (int side = -1; side <= 1; side += 2) {
+      if (k == 0 && side == 1) continue;
+      int32_t s = win->c + side * k;
+      if (s < win->s_lo || s > win->s_hi) continue;
+      int64_t lo = hit_offsets[layer_bank0 + s], hi = hit_offsets[layer_bank0 + s + 1];
+      if (lo < win->first) lo = win->first;
+      if (hi > win->end) hi = win->end;
+      for (int64_t i = lo; i < hi; ++i) out[n++] = i;
+    }
+  }
+  return n;
 }
 
 typedef struct {
@@ -180,17 +211,44 @@ static void fit_candidate(const ora_detector* det, const ora_extrap* x, const fl
   *chi2_out = chi2;
 }
 
-/* Selection order (Section V-B: prefer 4 hits over 3, then the lowest chi2); remaining ties go to
-   the lexicographically smallest hit-index tuple (missing hit = -1) so the choice is unique. */
+/* Selection order (Section V-B: prefer 4 hits over 3, then the lowest chi2).  A chi2 that is not a
+   number (a candidate whose hits all weigh 0 fits 0/0) comes after every number; remaining ties go
+   to the lexicographically smallest hit-index tuple (missing hit = -1), so the choice is unique. */
 static int better(int nhits, float chi2, const int32_t idx[NL], const ora_candidate* best)
 {
   if (!best->valid) return 1;
   if (nhits != best->nhits) return nhits > best->nhits;
-  if (chi2 < best->chi2) return 1;
-  if (chi2 > best->chi2) return 0;
+  int nan_new = isnan(chi2), nan_best = isnan(best->chi2);
+  if (nan_new != nan_best) return nan_best;
+  if (!nan_new) {
+    if (chi2 < best->chi2) return 1;
+    if (chi2 > best->chi2) return 0;
+  }
   for (int l = 0; l < NL; ++l)
     if (idx[l] != best->idx[l]) return idx[l] < best->idx[l];
   return 0;
+}
+
+static void consider(const ora_detector* det, const ora_extrap* x, const float* hit_u,
+                     const float* hit_weight, const int32_t idx[NL], ora_candidate* best)
+{
+  int n = 0;
+  for (int l = 0; l < NL; ++l) n += idx[l] >= 0;
+  float q, c2;
+  fit_candidate(det, x, hit_u, hit_weight, idx, &q, &c2);
+  if (better(n, c2, idx, best)) {
+    best->valid = 1; best->nhits = n; best->qop = q; best->chi2 = c2;
+    memcpy(best->idx, idx, sizeof(int32_t) * NL);
+  }
+}
+
+/* A hit takes part in the search when its strip covers the track's y (the VELO tolerance check that
+   Section V-A repeats in the tracking kernel) and its weight is a usable inverse variance: a
+   negative or NaN weight makes the hit unusable, like a strip that misses the track. */
+static int usable(const float* hit_y_begin, const float* hit_y_end, const float* hit_weight,
+                  int64_t i, float y)
+{
+  return hit_y_begin[i] <= y && y <= hit_y_end[i] && hit_weight[i] >= 0.0f;
 }
 
 /* anchor A, anchor B, completion C1, completion C2: forward uses the first and third panel as
@@ -198,6 +256,126 @@ static int better(int nhits, float chi2, const int32_t idx[NL], const ora_candid
 static const int DIRS[2][4] = {{0, 2, 1, 3}, {3, 1, 2, 0}};
 
 #define MAX_WIN 32
+
+/* Everything one track's search reads. */
+typedef struct {
+  const ora_detector* det;
+  const ora_params* par;
+  const float *u, *w, *yb, *ye;
+  float vtx;
+  ora_extrap x;
+  int64_t walk[NL][MAX_WIN];   /* window hits of each layer in walk order */
+  int nwalk[NL];
+} ora_track;
+
+/* Slope of an anchor pair and the test of Section V-B: the pair passes when its slope is within
+   slope_tol of the VELO slope. */
+static int pair_slope(const ora_track* T, int A, int B, int64_t iA, int64_t iB, float* mA_out,
+                      float* slope_out)
+{
+  const ora_detector* det = T->det;
+  const float inv_dz_ab = 1.0f / (det->z_layer[B] - det->z_layer[A]);
+  float mA = T->u[iA] + T->x.yl[A] * det->dxdy[A];
+  float mB = T->u[iB] + T->x.yl[B] * det->dxdy[B];
+  float slope = (mB - mA) * inv_dz_ab;
+  *mA_out = mA;
+  *slope_out = slope;
+  return fabsf(slope - T->vtx) <= T->par->slope_tol;
+}
+
+/* Completion hits of a passing pair in panel Cl: inside the tolerance window spanned by the pair
+   slope and the VELO slope extrapolated from the first anchor, widened by completion_tol.  Written
+   to out in walk order; returns their number. */
+static int compatible(const ora_track* T, int A, int Cl, float mA, float slope, int64_t* out)
+{
+  const ora_detector* det = T->det;
+  float d = det->z_layer[Cl] - det->z_layer[A];
+  float xt = mA + slope * d;
+  float xv = mA + T->vtx * d;
+  float lo = fminf(xt, xv) - T->par->completion_tol;
+  float hi = fmaxf(xt, xv) + T->par->completion_tol;
+  int n = 0;
+  for (int k = 0; k < T->nwalk[Cl]; ++k) {
+    int64_t i = T->walk[Cl][k];
+    if (!usable(T->yb, T->ye, T->w, i, T->x.yl[Cl])) continue;
+    float m = T->u[i] + T->x.yl[Cl] * det->dxdy[Cl];
+    if (lo <= m && m <= hi) out[n++] = i;
+  }
+  return n;
+}
+
+/* Every candidate of one direction (reading R11): both anchors, in each completion panel one
+   compatible hit or none, at least three hits; the best one under the selection order. */
+static void search_every_combination(const ora_track* T, int dir, ora_candidate* best)
+{
+  const int A = DIRS[dir][0], B = DIRS[dir][1], C[2] = {DIRS[dir][2], DIRS[dir][3]};
+  for (int a = 0; a < T->nwalk[A]; ++a) {
+    int64_t iA = T->walk[A][a];
+    if (!usable(T->yb, T->ye, T->w, iA, T->x.yl[A])) continue;
+    for (int b = 0; b < T->nwalk[B]; ++b) {
+      int64_t iB = T->walk[B][b];
+      if (!usable(T->yb, T->ye, T->w, iB, T->x.yl[B])) continue;
+      float mA, slope;
+      if (!pair_slope(T, A, B, iA, iB, &mA, &slope)) continue;
+      int64_t compat[2][MAX_WIN];
+      int ncompat[2];
+      for (int k = 0; k < 2; ++k) ncompat[k] = compatible(T, A, C[k], mA, slope, compat[k]);
+      for (int k1 = -1; k1 < ncompat[0]; ++k1) {
+        for (int k2 = -1; k2 < ncompat[1]; ++k2) {
+          if (k1 < 0 && k2 < 0) continue;
+          int32_t idx[NL];
+          idx[A] = (int32_t)iA;
+          idx[B] = (int32_t)iB;
+          idx[C[0]] = k1 >= 0 ? (int32_t)compat[0][k1] : -1;
+          idx[C[1]] = k2 >= 0 ? (int32_t)compat[1][k2] : -1;
+          consider(T->det, &T->x, T->u, T->w, idx, best);
+        }
+      }
+    }
+  }
+}
+
+/* The search as the paper runs it (Section V-B), reading R23: the combined ranges are walked in walk
+   order, anchor-A hits outermost; for each passing pair the compatible hit closest to the pair-slope
+   extrapolation is taken in each completion panel (the first in walk order on a tie); a pair with at
+   least one completion hit is a tracklet and is fitted; the search stops after max_tracklets
+   tracklets, the best of them by the selection order being kept. */
+static void search_as_the_paper(const ora_track* T, int dir, ora_candidate* best)
+{
+  const ora_detector* det = T->det;
+  const int A = DIRS[dir][0], B = DIRS[dir][1], C[2] = {DIRS[dir][2], DIRS[dir][3]};
+  int n_tracklets = 0;
+  for (int a = 0; a < T->nwalk[A]; ++a) {
+    int64_t iA = T->walk[A][a];
+    if (!usable(T->yb, T->ye, T->w, iA, T->x.yl[A])) continue;
+    for (int b = 0; b < T->nwalk[B]; ++b) {
+      int64_t iB = T->walk[B][b];
+      if (!usable(T->yb, T->ye, T->w, iB, T->x.yl[B])) continue;
+      float mA, slope;
+      if (!pair_slope(T, A, B, iA, iB, &mA, &slope)) continue;
+      int32_t pick[2] = {-1, -1};
+      for (int k = 0; k < 2; ++k) {
+        int64_t compat[MAX_WIN];
+        int nc = compatible(T, A, C[k], mA, slope, compat);
+        float xt = mA + slope * (det->z_layer[C[k]] - det->z_layer[A]);
+        float bd = 0.0f;
+        for (int q = 0; q < nc; ++q) {
+          float m = T->u[compat[q]] + T->x.yl[C[k]] * det->dxdy[C[k]];
+          float dist = fabsf(m - xt);
+          if (pick[k] < 0 || dist < bd) { pick[k] = (int32_t)compat[q]; bd = dist; }
+        }
+      }
+      if (pick[0] < 0 && pick[1] < 0) continue;
+      int32_t idx[NL];
+      idx[A] = (int32_t)iA;
+      idx[B] = (int32_t)iB;
+      idx[C[0]] = pick[0];
+      idx[C[1]] = pick[1];
+      consider(det, &T->x, T->u, T->w, idx, best);
+      if (++n_tracklets >= T->par->max_tracklets) return;
+    }
+  }
+}
 
 int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_events,
                      const uint32_t* hit_offsets, const float* hit_u, const float* hit_weight,
@@ -209,11 +387,18 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
 {
   if (!det || !par || det->n_layers != NL || det->n_sectors <= 0 || n_events < 0 ||
       par->max_hits < 1 || par->max_hits > MAX_WIN || par->n_sectors_search < 1 ||
-      par->n_sectors_search % 2 == 0 || !hit_offsets || !velo_offsets)
+      par->n_sectors_search % 2 == 0 || par->max_tracklets < 0 || !hit_offsets || !velo_offsets)
     return ORA_ERR_ARG;
   const int64_t S = det->n_sectors;
   const float W = par->w0 + par->kw / par->p_min;
   unsigned flags = 0;
+  ora_track T;
+  T.det = det;
+  T.par = par;
+  T.u = hit_u;
+  T.w = hit_weight;
+  T.yb = hit_y_begin;
+  T.ye = hit_y_end;
 
   for (int32_t e = 0; e < n_events; ++e) {
     /* window starts are stored relative to their (event, layer) as 16-bit values (Section V-A),
@@ -237,104 +422,24 @@ int ora_compass_find(const ora_detector* det, const ora_params* par, int32_t n_e
       if (active) active[t] = 0;
       if (overflow) continue;
 
-      ora_extrap x;
-      extrapolate(det, vx[t], vy[t], vtx[t], vty[t], &x);
-      if (!in_acceptance(det, &x)) continue;
+      extrapolate(det, vx[t], vy[t], vtx[t], vty[t], &T.x);
+      if (!in_acceptance(det, &T.x)) continue;
       if (active) active[t] = 1;
+      T.vtx = vtx[t];
 
-      int64_t wf[NL], we[NL];
       for (int l = 0; l < NL; ++l) {
-        find_window(det, par, hit_offsets, hit_u, ((int64_t)e * NL + l) * S, x.up[l], W,
-                    &wf[l], &we[l]);
-        if (win_first) win_first[(int64_t)t * NL + l] = (int32_t)wf[l];
-        if (win_size) win_size[(int64_t)t * NL + l] = (int32_t)(we[l] - wf[l]);
+        int64_t b0 = ((int64_t)e * NL + l) * S;
+        ora_window win;
+        find_window(det, par, hit_offsets, hit_u, b0, T.x.up[l], W, &win);
+        T.nwalk[l] = walk_order(par, hit_offsets, b0, &win, T.walk[l]);
+        if (win_first) win_first[(int64_t)t * NL + l] = (int32_t)win.first;
+        if (win_size) win_size[(int64_t)t * NL + l] = (int32_t)(win.end - win.first);
       }
 
+      /* forward first; the backward direction is only tried when the forward one found nothing */
       for (int dir = 0; dir < 2 && !best.valid; ++dir) {
-        const int A = DIRS[dir][0], B = DIRS[dir][1], C[2] = {DIRS[dir][2], DIRS[dir][3]};
-        int n_tracklets = 0;
-        const float inv_dz_ab = 1.0f / (det->z_layer[B] - det->z_layer[A]);
-        for (int64_t iA = wf[A]; iA < we[A]; ++iA) {
-          /* the strip must cover the track's y (the VELO tolerance check of Section V-A) */
-          if (!(hit_y_begin[iA] <= x.yl[A] && x.yl[A] <= hit_y_end[iA])) continue;
-          float mA = hit_u[iA] + x.yl[A] * det->dxdy[A];
-          for (int64_t iB = wf[B]; iB < we[B]; ++iB) {
-            if (!(hit_y_begin[iB] <= x.yl[B] && x.yl[B] <= hit_y_end[iB])) continue;
-            float mB = hit_u[iB] + x.yl[B] * det->dxdy[B];
-            float slope = (mB - mA) * inv_dz_ab;
-            if (!(fabsf(slope - vtx[t]) <= par->slope_tol)) continue;
-            /* tolerance window in each completion panel, spanned by the pair slope and the VELO
-               slope extrapolated from the first anchor, widened by completion_tol */
-            int32_t compat[2][MAX_WIN];
-            int ncompat[2] = {0, 0};
-            for (int k = 0; k < 2; ++k) {
-              int Cl = C[k];
-              float d = det->z_layer[Cl] - det->z_layer[A];
-              float xt = mA + slope * d;
-              float xv = mA + vtx[t] * d;
-              float lo = fminf(xt, xv) - par->completion_tol;
-              float hi = fmaxf(xt, xv) + par->completion_tol;
-              for (int64_t i = wf[Cl]; i < we[Cl]; ++i) {
-                if (!(hit_y_begin[i] <= x.yl[Cl] && x.yl[Cl] <= hit_y_end[i])) continue;
-                float m = hit_u[i] + x.yl[Cl] * det->dxdy[Cl];
-                if (lo <= m && m <= hi) compat[k][ncompat[k]++] = (int32_t)i;
-              }
-            }
-            if (par->max_tracklets > 0) {
-              /* the paper's search (Section V-B): in each completion panel the compatible hit
-                 closest to the pair-slope extrapolation (the first one on a tie); the pair makes a
-                 tracklet when at least one is found; the search stops after max_tracklets tracklets */
-              int32_t best_hit[2] = {-1, -1};
-              for (int k = 0; k < 2; ++k) {
-                float d = det->z_layer[C[k]] - det->z_layer[A];
-                float xt = mA + slope * d;
-                float bd = 0.0f;
-                for (int q = 0; q < ncompat[k]; ++q) {
-                  int32_t i = compat[k][q];
-                  float m = hit_u[i] + x.yl[C[k]] * det->dxdy[C[k]];
-                  float dist = fabsf(m - xt);
-                  if (best_hit[k] < 0 || dist < bd) { best_hit[k] = i; bd = dist; }
-                }
-              }
-              if (best_hit[0] < 0 && best_hit[1] < 0) continue;
-              int32_t idx[NL];
-              idx[A] = (int32_t)iA;
-              idx[B] = (int32_t)iB;
-              idx[C[0]] = best_hit[0];
-              idx[C[1]] = best_hit[1];
-              int n = 2 + (best_hit[0] >= 0) + (best_hit[1] >= 0);
-              float q, c2;
-              fit_candidate(det, &x, hit_u, hit_weight, idx, &q, &c2);
-              if (better(n, c2, idx, &best)) {
-                best.valid = 1; best.nhits = n; best.qop = q; best.chi2 = c2;
-                memcpy(best.idx, idx, sizeof idx);
-              }
-              if (++n_tracklets >= par->max_tracklets) goto direction_done;
-              continue;
-            }
-            /* every candidate: both anchors, each completion panel with one compatible hit or
-               none, at least three hits */
-            for (int k1 = -1; k1 < ncompat[0]; ++k1) {
-              for (int k2 = -1; k2 < ncompat[1]; ++k2) {
-                int n = 2 + (k1 >= 0) + (k2 >= 0);
-                if (n < 3) continue;
-                int32_t idx[NL];
-                idx[A] = (int32_t)iA;
-                idx[B] = (int32_t)iB;
-                idx[C[0]] = k1 >= 0 ? compat[0][k1] : -1;
-                idx[C[1]] = k2 >= 0 ? compat[1][k2] : -1;
-                float q, c2;
-                fit_candidate(det, &x, hit_u, hit_weight, idx, &q, &c2);
-                if (better(n, c2, idx, &best)) {
-                  best.valid = 1; best.nhits = n; best.qop = q; best.chi2 = c2;
-                  memcpy(best.idx, idx, sizeof idx);
-                }
-              }
-            }
-          }
-        }
-      direction_done:;
-        /* the backward direction is only tried when the forward one found nothing */
+        if (par->max_tracklets > 0) search_as_the_paper(&T, dir, &best);
+        else search_every_combination(&T, dir, &best);
       }
       if (best.valid) {
         for (int l = 0; l < NL; ++l) hit_idx[(int64_t)t * NL + l] = best.idx[l];

@@ -54,6 +54,7 @@ class EventBatch:
     n_layers_hit: np.ndarray       # i8[Nt], number of layers in which the VELO track left a hit
     delta_true: Optional[np.ndarray] = None   # f32[L*S] hidden per-sector x offsets (mm)
     truth: dict = field(default_factory=dict)
+    outside: Optional[np.ndarray] = None      # i8[Nt] how a track was put outside the planes (OUTSIDE_*)
 
     @property
     def n_tracks(self) -> int:
@@ -124,8 +125,40 @@ def _particles(rng, n):
 
 CHUNK_EVENTS = 1024   # events are drawn in blocks with a random stream of their own
 
+# Ways a VELO track is placed outside the planes (generator option outside_fraction): its straight
+# line leaves the plane height only at the last layer, only at the first layer, or the plane width
+# only at the last or only at the first layer; the other checked layer stays inside.
+OUTSIDE_NONE, OUTSIDE_Y_LAST, OUTSIDE_Y_FIRST, OUTSIDE_U_LAST, OUTSIDE_U_FIRST = 0, 1, 2, 3, 4
 
-def _chunk(rng, det, E, S, tracks, noise, hidden, delta_true, extra_padding_prob, with_truth):
+
+def _place_outside(rng, det, S, vx, vy, vtx, vty, fraction):
+    """Move a random `fraction` of the VELO states so that their straight line misses the planes in
+    one of the four OUTSIDE_* ways (chosen uniformly); returns the per-track code."""
+    n = vx.shape[0]
+    code = np.where(rng.random(n) < fraction, rng.integers(1, 5, n), 0).astype(np.int8)
+    dz0 = float(det.z_layer[0]) - float(det.z_velo)
+    dz3 = float(det.z_layer[3]) - float(det.z_velo)
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    beyond = rng.uniform(0.01, 40.0, n)      # how far past the edge (mm)
+    inside = rng.uniform(5.0, 150.0, n)      # how far inside the edge at the other layer (mm)
+    y_half, u_half = float(Y_HALF_MM), S * SECTOR_WIDTH_MM / 2.0
+    for c, half, last in ((OUTSIDE_Y_LAST, y_half, True), (OUTSIDE_Y_FIRST, y_half, False),
+                          (OUTSIDE_U_LAST, u_half, True), (OUTSIDE_U_FIRST, u_half, False)):
+        m = code == c
+        out_at = sign[m] * (half + beyond[m])
+        in_at = sign[m] * (half - inside[m])
+        at0, at3 = (in_at, out_at) if last else (out_at, in_at)
+        slope = (at3 - at0) / (dz3 - dz0)
+        start = at0 - slope * dz0
+        if c in (OUTSIDE_Y_LAST, OUTSIDE_Y_FIRST):
+            vy[m], vty[m] = start.astype(np.float32), slope.astype(np.float32)
+        else:
+            vx[m], vtx[m] = start.astype(np.float32), slope.astype(np.float32)
+    return code
+
+
+def _chunk(rng, det, E, S, tracks, noise, hidden, delta_true, extra_padding_prob, with_truth,
+           outside_fraction=0.0):
     """Draw E events; event indices and track ids are local to the block."""
     L = N_LAYERS
     n_velo = _counts(rng, tracks, E)
@@ -136,6 +169,8 @@ def _chunk(rng, det, E, S, tracks, noise, hidden, delta_true, extra_padding_prob
     Nv, Nh = int(n_velo.sum()), int(n_hidden.sum())
     vx, vy, vtx, vty, vqop = _particles(rng, Nv)
     hx, hy, htx, hty, hqop = _particles(rng, Nh)
+    outside = (_place_outside(rng, det, S, vx, vy, vtx, vty, outside_fraction)
+               if outside_fraction > 0 else np.zeros(Nv, np.int8))
     px = np.concatenate([vx, hx]).astype(np.float64)
     py = np.concatenate([vy, hy]).astype(np.float64)
     ptx = np.concatenate([vtx, htx]).astype(np.float64)
@@ -202,7 +237,7 @@ def _chunk(rng, det, E, S, tracks, noise, hidden, delta_true, extra_padding_prob
     order = np.argsort((bank << 24) | rng.integers(0, 1 << 24, bank.shape[0]))
     counts += np.bincount(pad_banks, minlength=NB)
     out = dict(words=words[order].astype(np.uint16), bank_counts=counts, n_velo=n_velo,
-               vx=vx, vy=vy, vtx=vtx, vty=vty, vqop=vqop, n_layers_hit=n_layers_hit)
+               vx=vx, vy=vy, vtx=vtx, vty=vty, vqop=vqop, n_layers_hit=n_layers_hit, outside=outside)
     if with_truth:
         ptruth = np.concatenate([np.arange(Nv, dtype=np.int64), np.full(Nh, TRUTH_HIDDEN, np.int64)])
         truth_id = np.concatenate([ptruth[pi], np.full(NN, TRUTH_NOISE, np.int64),
@@ -223,8 +258,11 @@ def generate(name: str = "tiny", n_events: Optional[int] = None, seed: Optional[
              with_truth: bool = True, n_sectors: Optional[int] = None,
              max_hits: Optional[int] = None, n_sectors_search: int = 5,
              tracks=None, noise=None, hidden=None, misalign_sigma: Optional[float] = None,
-             extra_padding_prob: float = 0.0) -> EventBatch:
+             extra_padding_prob: float = 0.0, outside_fraction: float = 0.0) -> EventBatch:
     """Generate a batch for recipe `name`; keyword arguments override the recipe.
+
+    outside_fraction > 0 places that fraction of the VELO tracks outside the planes at the first or
+    the last layer (EventBatch.outside records how); their hits follow the moved straight lines.
 
     Events are drawn in blocks of CHUNK_EVENTS, block c from the stream default_rng([seed, c]);
     the per-sector offsets (when the recipe has them) come from default_rng([seed, 1 << 20])."""
@@ -249,7 +287,8 @@ def generate(name: str = "tiny", n_events: Optional[int] = None, seed: Optional[
     def block(c):
         e0 = c * CHUNK_EVENTS
         return _chunk(np.random.default_rng([seed, c]), det, min(CHUNK_EVENTS, E - e0), S,
-                      tracks, noise, hidden, delta_true, extra_padding_prob, with_truth)
+                      tracks, noise, hidden, delta_true, extra_padding_prob, with_truth,
+                      outside_fraction)
 
     n_blocks = (E + CHUNK_EVENTS - 1) // CHUNK_EVENTS
     if n_blocks > 1:   # blocks are independent; numpy releases the GIL in the heavy steps
@@ -277,7 +316,7 @@ def generate(name: str = "tiny", n_events: Optional[int] = None, seed: Optional[
         velo_x=cat("vx", np.float32), velo_y=cat("vy", np.float32), velo_tx=cat("vtx", np.float32),
         velo_ty=cat("vty", np.float32), velo_offsets=velo_offsets,
         qop_true=cat("vqop", np.float64), n_layers_hit=cat("n_layers_hit", np.int8),
-        delta_true=delta_true)
+        delta_true=delta_true, outside=cat("outside", np.int8))
     if with_truth:
         tr = {}
         toff = 0
@@ -318,4 +357,5 @@ def take_events(batch: EventBatch, events) -> EventBatch:
         words=np.concatenate(words) if words else np.zeros(0, np.uint16), bank_offsets=bank_offsets,
         velo_x=batch.velo_x[tsel], velo_y=batch.velo_y[tsel], velo_tx=batch.velo_tx[tsel],
         velo_ty=batch.velo_ty[tsel], velo_offsets=velo_offsets, qop_true=batch.qop_true[tsel],
-        n_layers_hit=batch.n_layers_hit[tsel], delta_true=batch.delta_true)
+        n_layers_hit=batch.n_layers_hit[tsel], delta_true=batch.delta_true,
+        outside=batch.outside[tsel] if batch.outside is not None else None)

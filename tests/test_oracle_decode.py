@@ -145,3 +145,30 @@ def test_capacity_flagged_without_overrun():
     assert d["hit_offsets"][-1] == n
     full = _decode(b)
     assert np.array_equal(d["u"], full["u"][:n - 10])
+
+
+@pytest.mark.parametrize("name,n_events", [("tiny", 20), ("realistic", 3), ("pileup", 1)])
+def test_u_is_one_correctly_rounded_fma(name, n_events):
+    """u = fma(8*strip + fraction, pitch/8, u0) rounded once (Section IV, x at y = 0).  In binary64
+    the product and the sum are exact here: q < 2^12, pitch8 and u0 are binary32 values with
+    24-bit significands, the product's exponent range is small and every term is a multiple of
+    2^-30 below 2^14, so the exact value fits the 53-bit significand.  One rounding of that binary64
+    value to binary32 is therefore the correctly rounded fused result, bit for bit; a decoder that
+    rounds the product before the sum differs on some hits."""
+    b = synth.generate(name, n_events=n_events)
+    d = _decode(b)
+    det = b.detector
+    S = det.n_sectors
+    n = int(d["hit_offsets"][-1])
+    lid = d["lhcbid"][:n].astype(np.int64)
+    layer, sector = lid >> 28, (lid >> 12) & 0xFFFF
+    q = ((lid >> 3) & 0x1FF) * 8 + (lid & 7)
+    p8 = np.float64(np.float32(det.pitch8))
+    u0 = np.asarray(det.u0, np.float32).astype(np.float64)[layer * S + sector]
+    exact = q.astype(np.float64) * p8 + u0
+    # the binary64 sum is exact: subtracting the terms back leaves no remainder
+    assert np.array_equal(exact - u0, q.astype(np.float64) * p8)
+    assert np.array_equal(d["u"][:n].view(np.uint32), exact.astype(np.float32).view(np.uint32))
+    two_roundings = (np.float32(q.astype(np.float32) * np.float32(det.pitch8)) +
+                     np.asarray(det.u0, np.float32)[layer * S + sector])
+    assert (two_roundings != d["u"][:n]).any()

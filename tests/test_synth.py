@@ -92,3 +92,23 @@ def test_take_events_matches_slices():
         t0, t1 = b.velo_offsets[e], b.velo_offsets[e + 1]
         u0, u1 = sub.velo_offsets[k], sub.velo_offsets[k + 1]
         assert np.array_equal(sub.velo_tx[u0:u1], b.velo_tx[t0:t1])
+
+
+def test_outside_fraction_places_tracks_outside_the_planes():
+    """The generator's outside_fraction option moves VELO states so that their straight line leaves
+    the planes at exactly one of the two checked layers; the oracle filters them out (Section V-A)
+    and keeps every other track.  Without the option the batch is unchanged."""
+    import oracle
+    from synth.events import OUTSIDE_NONE
+    b0 = synth.generate("realistic", n_events=30, with_truth=False)
+    b = synth.generate("realistic", n_events=30, with_truth=False, outside_fraction=0.4)
+    assert np.array_equal(b0.words, synth.generate("realistic", n_events=30, with_truth=False).words)
+    assert (b0.outside == OUTSIDE_NONE).all()
+    codes = np.bincount(b.outside, minlength=5)
+    assert codes[1:].min() > 0.05 * b.n_tracks      # every way is well represented
+    d = oracle.decode(b.detector, b.words, b.bank_offsets, b.n_events)
+    c = oracle.compass(b.detector, b.params, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx,
+                       b.velo_ty, b.velo_offsets, with_windows=True)
+    assert np.array_equal(c["active"] == 0, b.outside != OUTSIDE_NONE)
+    # the moved tracks still leave hits in the layers they cross inside the planes
+    assert (b.n_layers_hit[b.outside != OUTSIDE_NONE] >= 3).mean() > 0.2
