@@ -113,6 +113,26 @@ utc_status ut_decode(const utc_geometry* geom, const uint16_t* words, const uint
                      const utc_launch_config* launch, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * ut_decode_noalloc — ut_decode for callers that cannot allocate device memory (code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and errors as ut_decode, without the workspace: the unit sums and bases go to a fixed scratch
+ * array inside the library, 4 * (8 * UTC_NOALLOC_MAX_EVENTS + 1) bytes (about 1 MiB) of device
+ * memory on each GPU the call runs on, held until the process ends.  The call allocates nothing;
+ * its first call on a device looks up that device's copy of the array (hipGetSymbolAddress, with the
+ * device current).  n_events > UTC_NOALLOC_MAX_EVENTS returns UTC_ERR_ARG; a failed lookup returns
+ * UTC_ERR_HIP.  Every call on one GPU shares the array, so calls that may run at the same time on
+ * one GPU (on different streams, or from different threads) race and give wrong results: order them
+ * on one stream, or use ut_decode with a workspace each.
+ * --------------------------------------------------------------------------------------------- */
+#define UTC_NOALLOC_MAX_EVENTS 32768
+
+utc_status ut_decode_noalloc(const utc_geometry* geom, const uint16_t* words,
+                             const uint32_t* bank_offsets, int32_t n_events, int64_t hit_capacity,
+                             uint32_t* hit_offsets, uint32_t* lhcbid, float* z, float* u,
+                             float* y_begin, float* y_end, float* weight, uint32_t* error_flags,
+                             const utc_launch_config* launch, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
  * compass_find — Section V: per VELO track, hit windows in the four layers (V-A), tracklet search
  * with the p-kick chi2 fit and selection (V-B).
  *

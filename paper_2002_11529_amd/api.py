@@ -26,6 +26,7 @@ FLAG_CAPACITY = 2
 FLAG_LAYER_OVERFLOW = 4
 FLAG_BANK_SIZE = 8
 MAX_BANK_WORDS = 8192
+NOALLOC_MAX_EVENTS = 32768
 
 
 class UtcGeometry(ctypes.Structure):
@@ -60,6 +61,8 @@ def library():
     L.ut_decode_workspace_bytes.argtypes = [_i32, _i32]
     L.ut_decode.restype = ctypes.c_int
     L.ut_decode.argtypes = [_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P]
+    L.ut_decode_noalloc.restype = ctypes.c_int
+    L.ut_decode_noalloc.argtypes = [_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.compass_find_workspace_bytes.restype = _sz
     L.compass_find_workspace_bytes.argtypes = [_i32, _i64]
     L.compass_find.restype = ctypes.c_int
@@ -206,6 +209,28 @@ def ut_decode(geom: Geometry, words, bank_offsets, n_events: int, hit_capacity: 
                      _ptr(out["weight"], "f32"), _ptr(error_flags, "i32"), _ptr(workspace),
                      workspace.numel(), _launch(launch), _stream(stream))
     _check(st, "ut_decode")
+    return out
+
+
+def ut_decode_noalloc(geom: Geometry, words, bank_offsets, n_events: int, out,
+                      hit_capacity: Optional[int] = None, error_flags=None, launch=None, stream=None):
+    """ut_decode through the entry point that allocates nothing: the caller passes every output
+    (`out`, a dict of device tensors as ut_decode returns it, and `error_flags`); the library's
+    fixed per-GPU scratch array replaces the workspace.  Calls on one GPU must not overlap."""
+    L = library()
+    n_banks = n_events * 4 * geom.n_sectors
+    if bank_offsets.shape[0] != n_banks + 1:
+        raise ValueError("bank_offsets must have n_events*4*S + 1 entries")
+    if error_flags is None:
+        raise ValueError("error_flags must be passed (this entry point allocates nothing)")
+    cap = int(words.shape[0]) if hit_capacity is None else int(hit_capacity)
+    st = L.ut_decode_noalloc(geom.ref, _ptr(words, "i16"), _ptr(bank_offsets, "i32"), n_events, cap,
+                             _ptr(out["hit_offsets"], "i32"), _ptr(out["lhcbid"], "i32"),
+                             _ptr(out.get("z"), "f32"), _ptr(out["u"], "f32"),
+                             _ptr(out.get("y_begin"), "f32"), _ptr(out.get("y_end"), "f32"),
+                             _ptr(out["weight"], "f32"), _ptr(error_flags, "i32"), _launch(launch),
+                             _stream(stream))
+    _check(st, "ut_decode_noalloc")
     return out
 
 

@@ -10,6 +10,8 @@
 // The paper's seven kernels (count, three-kernel prefix sum, pre-decode, find permutation, decode
 // in order; Table "Kernel configuration for UT decoding") become these two; the order inside a bank
 // is by x (the word value) rather than by y.
+#include <mutex>
+
 #include "decode_unit.hpp"
 
 namespace utc {
@@ -104,26 +106,17 @@ extern "C" size_t ut_decode_workspace_bytes(int32_t n_events, int32_t n_sectors)
   return ((2 * units + 1) * sizeof(uint32_t) + 255) / 256 * 256;
 }
 
-extern "C" utc_status ut_decode(const utc_geometry* geom, const uint16_t* words,
+// The three launches of a decode call; unit_sum holds 2 * n_events * 4 + 1 words of device memory
+// (the unit sums, then the unit bases), whatever its content.
+static utc_status decode_launch(const utc_geometry* geom, const uint16_t* words,
                                 const uint32_t* bank_offsets, int32_t n_events, int64_t hit_capacity,
                                 uint32_t* hit_offsets, uint32_t* lhcbid, float* z, float* u,
                                 float* y_begin, float* y_end, float* weight, uint32_t* error_flags,
-                                void* workspace, size_t workspace_bytes,
-                                const utc_launch_config* launch, hipStream_t stream)
+                                uint32_t* unit_sum, const utc_launch_config* launch,
+                                hipStream_t stream)
 {
-  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
-      !geom->u0 || n_events < 0 || hit_capacity < 0 || !bank_offsets || !hit_offsets)
-    return UTC_ERR_ARG;
-  if (n_events > 0 && hit_capacity > 0 && (!words || !lhcbid || !u || !weight))
-    return UTC_ERR_ARG;
-  if (launch && (launch->block < 64 || launch->block > 1024 || launch->block % 64 || launch->grid < 0))
-    return UTC_ERR_ARG;
-  if ((int64_t)n_events * kLayers > INT32_MAX / 2) return UTC_ERR_ARG;
-  const size_t need = ut_decode_workspace_bytes(n_events, geom->n_sectors);
-  if (!workspace || workspace_bytes < need) return UTC_ERR_WORKSPACE;
   const int S = geom->n_sectors;
   const int n_units = n_events * kLayers;
-  uint32_t* unit_sum = static_cast<uint32_t*>(workspace);
   uint32_t* unit_base = unit_sum + n_units;
   const Geom g = make_geom(*geom);
   const int cap = chunk_words(S);
@@ -157,4 +150,88 @@ extern "C" utc_status ut_decode(const utc_geometry* geom, const uint16_t* words,
                        n_units, cap, hit_capacity, unit_base, hit_offsets, out, error_flags);
   }
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
+}
+
+// Host-side argument checks shared by ut_decode and ut_decode_noalloc.
+static bool decode_args_ok(const utc_geometry* geom, const uint16_t* words,
+                           const uint32_t* bank_offsets, int32_t n_events, int64_t hit_capacity,
+                           const uint32_t* hit_offsets, const uint32_t* lhcbid, const float* u,
+                           const float* weight, const utc_launch_config* launch)
+{
+  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
+      !geom->u0 || n_events < 0 || hit_capacity < 0 || !bank_offsets || !hit_offsets)
+    return false;
+  if (n_events > 0 && hit_capacity > 0 && (!words || !lhcbid || !u || !weight)) return false;
+  if (launch && (launch->block < 64 || launch->block > 1024 || launch->block % 64 || launch->grid < 0))
+    return false;
+  if ((int64_t)n_events * kLayers > INT32_MAX / 2) return false;
+  return true;
+}
+
+extern "C" utc_status ut_decode(const utc_geometry* geom, const uint16_t* words,
+                                const uint32_t* bank_offsets, int32_t n_events, int64_t hit_capacity,
+                                uint32_t* hit_offsets, uint32_t* lhcbid, float* z, float* u,
+                                float* y_begin, float* y_end, float* weight, uint32_t* error_flags,
+                                void* workspace, size_t workspace_bytes,
+                                const utc_launch_config* launch, hipStream_t stream)
+{
+  if (!decode_args_ok(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, u,
+                      weight, launch))
+    return UTC_ERR_ARG;
+  const size_t need = ut_decode_workspace_bytes(n_events, geom->n_sectors);
+  if (!workspace || workspace_bytes < need) return UTC_ERR_WORKSPACE;
+  return decode_launch(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, z, u,
+                       y_begin, y_end, weight, error_flags, static_cast<uint32_t*>(workspace),
+                       launch, stream);
+}
+
+// ---- ut_decode without a workspace argument ----
+// The unit sums and bases live in a fixed device array of the library (one copy per GPU, held
+// until the process ends).  In host code `scratch` names a host-side stand-in, not the device
+// copy: kernels get the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchWords = 2 * (size_t)UTC_NOALLOC_MAX_EVENTS * kLayers + 1;
+static __device__ __align__(256) uint32_t scratch[kNoAllocScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Address of the calling device's `scratch`, looked up once per device (with that device
+// current); nullptr when HIP reports an error.
+uint32_t* device_scratch()
+{
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<uint32_t*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" utc_status ut_decode_noalloc(const utc_geometry* geom, const uint16_t* words,
+                                        const uint32_t* bank_offsets, int32_t n_events,
+                                        int64_t hit_capacity, uint32_t* hit_offsets,
+                                        uint32_t* lhcbid, float* z, float* u, float* y_begin,
+                                        float* y_end, float* weight, uint32_t* error_flags,
+                                        const utc_launch_config* launch, hipStream_t stream)
+{
+  if (!decode_args_ok(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, u,
+                      weight, launch))
+    return UTC_ERR_ARG;
+  if (n_events > UTC_NOALLOC_MAX_EVENTS) return UTC_ERR_ARG;
+  uint32_t* ws = device_scratch();
+  if (!ws) return UTC_ERR_HIP;
+  return decode_launch(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, z, u,
+                       y_begin, y_end, weight, error_flags, ws, launch, stream);
 }

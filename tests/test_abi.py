@@ -163,3 +163,19 @@ def test_host_checks_of_every_entry_point():
     assert cons(-1, cons_ws) == -1
     assert cons(10, cons_ws, nhits=None) == -1
     assert cons(10, cons_ws - 1) == -2
+
+
+def test_noalloc_decode_rejects_on_the_host():
+    """ut_decode_noalloc checks its arguments, and the event count against its fixed scratch,
+    before it touches a GPU."""
+    import paper_2002_11529_amd.api as api
+    L = api.library()
+    g = api.UtcGeometry()
+    g.n_layers, g.n_sectors, g.u0 = 4, 32, 16  # a non-NULL placeholder; never dereferenced here
+    one = ctypes.c_void_p(64)
+    assert L.ut_decode_noalloc(None, one, one, 1, 10, one, one, one, one, one, one, one, None,
+                               None, None) == -1
+    assert L.ut_decode_noalloc(ctypes.byref(g), one, one, -1, 10, one, one, one, one, one, one,
+                               one, None, None, None) == -1
+    assert L.ut_decode_noalloc(ctypes.byref(g), one, one, api.NOALLOC_MAX_EVENTS + 1, 10, one,
+                               one, one, one, one, one, one, None, None, None) == -1
