@@ -38,7 +38,8 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
   uint32_t* s_next = s_hoff + nb + 1;   // group counter, in the padding after the offsets
   uint32_t* s_event = s_hoff + nb + 2;  // the workgroup's next event (persistent grids)
   char* gbase = reinterpret_cast<char*>(s_u + u_cap);
-  const GroupScratch gs = carve_group(gbase + (size_t)wid * group_scratch_bytes(p.max_hits), p.max_hits);
+  const GroupScratch gs = carve_group(gbase + (size_t)wid * group_scratch_bytes(p.max_hits, kGreedy),
+                                      p.max_hits, kGreedy);
 
   // a persistent grid (ev_counter set, cleared to gridDim.x beforehand) takes events 0..grid-1 in
   // order and then claims the next event whenever a workgroup finishes one, so uneven events
@@ -138,9 +139,9 @@ __global__ void k_compass_start(uint32_t* ev_counter, uint32_t grid) {
   if (threadIdx.x == 0) *ev_counter = grid;
 }
 
-size_t compass_lds_bytes(int S, int max_hits, int waves, int u_cap) {
+size_t compass_lds_bytes(int S, int max_hits, int waves, int u_cap, bool greedy) {
   const size_t hoff = 4 * (size_t)(((kLayers * S + 1) + 3) & ~3);
-  return hoff + 4 * (size_t)u_cap + (size_t)waves * group_scratch_bytes(max_hits);
+  return hoff + 4 * (size_t)u_cap + (size_t)waves * group_scratch_bytes(max_hits, greedy);
 }
 
 }  // namespace utc
@@ -189,6 +190,7 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   p.slope_tol = params->slope_tol;
   p.eps = params->completion_tol;
   p.max_tracklets = params->max_tracklets;
+  const bool greedy = p.max_tracklets > 0;
   // the pruning bound needs positive kick factors
   p.prune = 1;
   for (int l = 0; l < kLayers; ++l)
@@ -196,16 +198,16 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   // without a given launch shape, fewer wavefronts per workgroup when the bank offsets of a large
   // geometry and the tiles of large windows do not fit the LDS of four
   int block = launch ? launch->block : 256;
-  while (!launch && block > kWave && compass_lds_bytes(g.S, p.max_hits, block / kWave, 0) > 160 * 1024)
+  while (!launch && block > kWave && compass_lds_bytes(g.S, p.max_hits, block / kWave, 0, greedy) > 160 * 1024)
     block -= kWave;
   const int waves = block / kWave;
   // stage u of events up to u_cap hits, keeping the workgroup's LDS at 10 KiB per wavefront (four
   // 256-thread workgroups share a CU's 160 KiB, the occupancy the kernel's registers allow);
   // larger events search global memory
   const size_t budget = (size_t)waves * 10 * 1024;
-  const size_t fixed = compass_lds_bytes(g.S, p.max_hits, waves, 0);
+  const size_t fixed = compass_lds_bytes(g.S, p.max_hits, waves, 0, greedy);
   const int u_cap = fixed < budget ? (int)((budget - fixed) / sizeof(float)) / 64 * 64 : 0;
-  const size_t lds = compass_lds_bytes(g.S, p.max_hits, waves, u_cap);
+  const size_t lds = compass_lds_bytes(g.S, p.max_hits, waves, u_cap, greedy);
   if (lds > 160 * 1024) return UTC_ERR_ARG;
   (void)hipGetLastError();  // report only errors of this call
   const int grid = (launch && launch->grid > 0) ? launch->grid : n_events;

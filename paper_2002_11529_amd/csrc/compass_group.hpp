@@ -76,15 +76,20 @@ struct GroupScratch {
   uint32_t* bm2;      // [64] their completion masks in layer C2
   uint32_t* boff;     // [65] candidate offsets of the batch
   uint32_t* mk;       // [64] pair starting at each candidate slot of a chunk (index + 1, 0 = none)
+  // the paper's search only: window slots in the order the search walks them (central sector
+  // first, see build_walk_order), walk[p] = slot at walk position p, iwalk[slot] = its position
+  uint8_t* walk;      // [max_hits][64]
+  uint8_t* iwalk;     // [max_hits][64]
 };
 
-__host__ __device__ inline size_t group_scratch_bytes(int max_hits) {
+__host__ __device__ inline size_t group_scratch_bytes(int max_hits, bool greedy) {
   const size_t b = 16 * kGroupTracks + 8 * 64 + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
-                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65 + 4 * 64;
+                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65 + 4 * 64 +
+                   (greedy ? 2 * 64 * (size_t)max_hits : 0);
   return (b + 15) / 16 * 16;
 }
 
-__device__ inline GroupScratch carve_group(char* p, int max_hits) {
+__device__ inline GroupScratch carve_group(char* p, int max_hits, bool greedy) {
   GroupScratch s;
   s.best = reinterpret_cast<unsigned long long*>(p);
   s.lbk = s.best + kGroupTracks;
@@ -101,10 +106,24 @@ __device__ inline GroupScratch carve_group(char* p, int max_hits) {
   s.bm2 = s.bm1 + 64;
   s.boff = s.bm2 + 64;
   s.mk = s.boff + 65;
+  s.walk = greedy ? reinterpret_cast<uint8_t*>(s.mk + 64) : nullptr;
+  s.iwalk = greedy ? s.walk + 64 * max_hits : nullptr;
   return s;
 }
 
 __device__ inline int tile_at(int t, int l, int j) { return j * 64 + t * 4 + l; }
+
+// Walk position <-> window slot of lane 4t+l (the paper's search only).
+__device__ inline uint32_t walk_slot(const GroupScratch& s, int t, int l, uint32_t pos) {
+  return s.walk[tile_at(t, l, (int)pos)];
+}
+
+// A mask of window slots of lane 4t+l as a mask of walk positions.
+__device__ inline uint32_t to_walk_mask(const GroupScratch& s, int t, int l, uint32_t m) {
+  uint32_t w = 0u;
+  for (; m; m &= m - 1u) w |= 1u << s.iwalk[tile_at(t, l, __builtin_ctz(m))];
+  return w;
+}
 
 // anchor A, anchor B, completion C1, completion C2; forward then backward (panel order reversed)
 __device__ inline void dir_layers(int dir, int& A, int& B, int& C1, int& C2) {
@@ -339,15 +358,15 @@ __device__ inline uint32_t nearest_slot(const Geom& g, const GroupScratch& s, in
 }
 
 // The slot of mask m in layer Cl whose x is closest to the pair-slope extrapolation from the first
-// anchor (the first one on a tie), as a one-bit mask; 0 for an empty mask.
+// anchor (the first one in walk order on a tie), as a one-bit mask; 0 for an empty mask.
 __device__ inline uint32_t closest_slot_mask(const Geom& g, const GroupScratch& s, int t, int A, int Cl,
                                              uint32_t m, float mA, float slope) {
   const float xt = mA + slope * (g.z_layer[Cl] - g.z_layer[A]);
   uint32_t arg = 0u;
   float bd = 0.0f;
   bool any = false;
-  for (uint32_t mm = m; mm; mm &= mm - 1) {
-    const uint32_t j = (uint32_t)__builtin_ctz(mm);
+  for (uint32_t wm = to_walk_mask(s, t, Cl, m); wm; wm &= wm - 1) {
+    const uint32_t j = walk_slot(s, t, Cl, (uint32_t)__builtin_ctz(wm));
     const float dist = fabsf(s.tm[tile_at(t, Cl, (int)j)] - xt);
     if (!any || dist < bd) { arg = j; bd = dist; any = true; }
   }
@@ -534,11 +553,13 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
     const uint32_t tr1 = wave_inclusive_max(mtr);
     if (it < total) {
       const int tt = (int)tr1 - 1;
-      const uint32_t jA = it - s.poff[tt];
+      // the paper's search takes the anchor-A hits in walk order, the exhaustive one in slot order
+      const uint32_t jA = nhits == 0 ? walk_slot(s, tt, A, it - s.poff[tt]) : it - s.poff[tt];
       head = (uint32_t)tt | (jA << 8);
       if ((s.umask[tt * 4 + A] >> jA) & 1u) {
         const float mA = s.tm[tile_at(tt, A, (int)jA)];
         rem = slope_range(s, tt, B, mA, inv_dz_ab, s.tx[tt], p.slope_tol) & s.umask[tt * 4 + B];
+        if (nhits == 0) rem = to_walk_mask(s, tt, B, rem);   // anchor-B hits in walk order too
       }
     }
     while (wave_any(rem != 0u)) {
@@ -550,7 +571,8 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
       const uint32_t room = (uint32_t)kWave - min(o, (uint32_t)kWave);
       const uint32_t take = min(c, room);
       for (uint32_t k = 0; k < take; ++k) {
-        const uint32_t jB = (uint32_t)__builtin_ctz(rem);
+        uint32_t jB = (uint32_t)__builtin_ctz(rem);
+        if (nhits == 0) jB = walk_slot(s, (int)(head & 0xFFu), B, jB);
         rem &= rem - 1u;
         s.bp[o + k] = head | (jB << 16);
       }
@@ -638,11 +660,15 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   // window (Section V-A): central sector and neighbours, [up - W, up + W], nearest max_hits hits
   uint32_t wf = 0;
   int wn = 0;
+  int wc = 0, ws_lo = 0, ws_hi = -1;   // central sector and the allowed sector range
   if (active) {
     const float ts = floorf((up - g.u_min) * g.inv_sector_width);
     const int c = ts < 0.0f ? 0 : (ts > (float)(S - 1) ? S - 1 : (int)ts);
     const int s_lo = c - p.half < 0 ? 0 : c - p.half;
     const int s_hi = c + p.half > S - 1 ? S - 1 : c + p.half;
+    wc = c;
+    ws_lo = s_lo;
+    ws_hi = s_hi;
     const uint32_t H0 = ev.hoff[l * S + s_lo], H1 = ev.hoff[l * S + s_hi + 1];
     const float lo = up - p.W, hi = up + p.W;
     // both edges in one loop (two independent searches over [H0, H1), loads issued together);
@@ -737,6 +763,32 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   }
   s.umask[lane] = umask;
   s.wmax[lane] = wm;
+  if constexpr (kGreedy) {
+    // walk order of the window (Section V-B: the combined sector ranges with the central sector
+    // first, then the neighbours at growing distance, the left one first; ascending x inside a
+    // sector).  The window [wf, wf + wn) lies inside the allowed sectors, so every slot is placed
+    // by distance p.half; both arrays start as the identity, so that with hit offsets that are not
+    // ascending every entry still names a slot of the window.
+    for (int j = 0; j < wn; ++j) {
+      s.walk[tile_at(t, l, j)] = (uint8_t)j;
+      s.iwalk[tile_at(t, l, j)] = (uint8_t)j;
+    }
+    uint32_t pos = 0;
+    const uint32_t wend = wf + (uint32_t)wn;
+    for (int d = 0; d <= p.half && pos < (uint32_t)wn; ++d) {
+      for (int side = -1; side <= 1; side += 2) {
+        if (d == 0 && side == 1) continue;
+        const int sec = wc + side * d;
+        if (sec < ws_lo || sec > ws_hi) continue;
+        const uint32_t lo = max(ev.hoff[l * S + sec], wf);
+        const uint32_t hi = min(ev.hoff[l * S + sec + 1], wend);
+        for (uint32_t k = lo; k < hi && pos < (uint32_t)wn; ++k, ++pos) {
+          s.walk[tile_at(t, l, (int)pos)] = (uint8_t)(k - wf);
+          s.iwalk[tile_at(t, l, (int)(k - wf))] = (uint8_t)pos;
+        }
+      }
+    }
+  }
   wave_sync();
 
   // tracklets (Section V-B): forward anchors first; backward only where forward found nothing

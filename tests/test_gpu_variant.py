@@ -38,3 +38,19 @@ def test_variant_matches_oracle(decoded, budget):
     assert r["error_flags"] == 0
     assert_compass_equal(r, c)
     assert (c["nhits"] > 0).sum() > 0
+
+
+@pytest.mark.parametrize("m,budget", [(1, 0), (2, 0), (4, 0), (1, 1), (2, 2), (4, 4), (16, 16)])
+def test_sweep_configurations(decoded, m, budget):
+    """The configurations of the efficiency sweep (windows of m hits; the exhaustive search, or the
+    paper's search with a budget of m tracklets) on every workload."""
+    b, dv, geom, hits, d = decoded
+    p = synth.make_compass_params(p_min_mev=float(b.params.p_min), max_hits=m,
+                                  n_sectors_search=b.params.n_sectors_search, max_tracklets=budget)
+    res = utc.compass_find(geom, p, b.n_events, hits, *dv["vel"], dv["velo_offsets"])
+    torch.cuda.synchronize()
+    r = {k: v.cpu().numpy() for k, v in res.items()}
+    c = oracle.compass(b.detector, p, b.n_events, d, b.velo_x, b.velo_y, b.velo_tx, b.velo_ty,
+                       b.velo_offsets)
+    assert_compass_equal(r, c)
+    assert (c["nhits"] > 0).sum() > 0
