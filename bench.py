@@ -2,9 +2,11 @@
 """Throughput of the UT chain on one MI355X: raw-bank decoding + Compass tracking + the fit-chi2
 forward/backward pass, over one batch of synthetic LHCb-shaped events per step.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload realistic]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched] [--also realistic,pileup]
 
-Prints one JSON line.  `value` = events per second of the whole step with inputs resident in HBM.
+Prints one JSON line.  `value` = events per second of the whole step with inputs resident in HBM,
+on the batch of 20000 events of uneven size (the largest one-GPU workload with the default window);
+the realistic and pile-up workloads are timed the same way and reported as extra keys.
 Per-call durations come from HIP events on the stream the library launches on; the dominant call's
 algorithmic bytes over its average duration give the roofline fraction against the 8 TB/s HBM peak.
 The CPU baseline is the plain oracle timed on a bounded sample of the same workload.
@@ -108,13 +110,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="realistic")
+    ap.add_argument("--workload", default="batched",
+                    help="the workload of the headline figure (batched: 20000 uneven events)")
+    ap.add_argument("--also", default="realistic,pileup",
+                    help="comma-separated further workloads timed the same way (extra keys of the line)")
     ap.add_argument("--events", type=int, default=None)
     ap.add_argument("--rotate", type=int, default=3,
                     help="input/output copies used round-robin so the working set exceeds the 256 MB Infinity Cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of HIP graph replays")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-events", type=int, default=2000,
+                    help="events of the headline workload the CPU oracle is timed on")
     ap.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the tuned ones")
     ap.add_argument("--no-per-event", action="store_true", help="skip the one-event-at-a-time comparison")
     ap.add_argument("--streams", type=int, default=0,
@@ -142,7 +149,6 @@ def main():
               "the path shards by event ranges with no exchange; multi-GPU runs are not "
               "supported.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -152,16 +158,94 @@ def main():
         sweep(args)
         return
 
+    head = measure_chain(args, args.workload, full=True)
+    b, E, S, Nt = head["batch"], head["E"], head["S"], head["Nt"]
+    copy_bw = None if args.no_copy_bandwidth else copy_bandwidth()
+    dom = head["dominant"]
+    kern = KERNEL_OF_CALL[dom]
+    achieved = head["per_call_GBps"][dom]
+    out = {
+        "metric": "events/s UT decode+Compass @1 GPU (HBM GB/s); fwd+bwd fitted tracks/s",
+        "value": round(head["value"], 1),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": head["workload"],
+                   "step": "ut_decode + compass_find + compass_fit_grad(fwd+bwd)",
+                   "rotated_copies": head["rotated_copies"], "streams": head["streams"],
+                   "search_launch_timed": head["search_launch_timed"],
+                   "stream_trials_ms_per_step": head["stream_trials"]},
+        "roofline": {"bound": "hbm", "kernel": kern, "call": dom,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(kern, args.workload, head["shape_tags"].get(kern)),
+                     "copy_GBps": round(copy_bw, 1) if copy_bw else None,
+                     "frac_of_copy": round(achieved / copy_bw, 4) if copy_bw else None,
+                     "valu_issue": valu_issue(kern, args.workload, head["calls_ms"][dom],
+                                              head["shape_tags"].get(kern))},
+        "calls_ms": {n: round(float(m), 5) for n, m in head["calls_ms"].items()},
+        "calls_algorithmic_GBps": {n: round(v, 1) for n, v in head["per_call_GBps"].items()},
+        "step_algorithmic_GBps": round(head["step_GBps"], 1),
+        "timing": head["timing"],
+        "launch": head["launch"],
+        "batched_vs_per_event": head["per_event"],
+        "compact_hits": head["compact"],
+        "found_fraction": round(head["found_fraction"], 5),
+        "wall_s": round(head["wall_s"], 4),
+    }
+    out["event_cut_and_consolidation"] = head["select"]
+    head = None
+    torch.cuda.empty_cache()
+    # the other synthetic workloads, timed the same way (graph replay, tuned shapes, best stream
+    # count), without the per-event and compact comparisons
+    others = {}
+    for wl in [w for w in args.also.split(",") if w and w != args.workload]:
+        r = measure_chain(args, wl, full=False)
+        others[wl] = {"workload": r["workload"], "events_per_s": round(r["value"], 1),
+                      "ms_per_step": round(r["ms_per_step"], 5), "streams": r["streams"],
+                      "calls_ms": {n: round(float(m), 5) for n, m in r["calls_ms"].items()},
+                      "calls_algorithmic_GBps": {n: round(v, 1) for n, v in r["per_call_GBps"].items()},
+                      "step_algorithmic_GBps": round(r["step_GBps"], 1),
+                      "step_frac_of_hbm_peak": round(r["step_GBps"] / HBM_PEAK_GBS, 4),
+                      "found_fraction": round(r["found_fraction"], 5), "launch": r["launch"]}
+        r = None
+        torch.cuda.empty_cache()
+    out["other_workloads"] = others
+    if not args.no_fitgrad:
+        out["fitgrad"] = bench_fitgrad(args, torch.device("cuda:0"))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds, args.cpu_events)
+    print(json.dumps(out), flush=True)
+
+
+def measure_chain(args, workload, full):
+    """One workload: decode + Compass + fit-chi2 fwd+bwd per step over rotated buffer copies, HIP
+    graph replays on the fastest of 1-3 streams; per-call durations from HIP events on eager
+    launches.  With `full`, also the compact hit form, the per-event launches and the steps either
+    side of the chain."""
+    import numpy as np
+    import torch
+
     import synth
     import paper_2002_11529_amd as utc
 
     dev = torch.device("cuda:0")
-    b = synth.generate(args.workload, n_events=args.events, with_truth=False)
+    b = synth.generate(workload, n_events=args.events if workload == args.workload else None,
+                       with_truth=False)
     E, S = b.n_events, b.detector.n_sectors
     NB = E * 4 * S
     geom = utc.Geometry(b.detector, dev)
     params = utc.compass_params(b.params)
     L = utc.library()
+    print(f"[bench] {workload}: {E} events, {b.n_tracks} tracks, {b.n_words} words", file=sys.stderr,
+          flush=True)
 
     NS_CHOICES = (1, 2, 3) if args.streams <= 0 else (args.streams,)
     LCM = int(np.lcm.reduce(NS_CHOICES))
@@ -260,7 +344,6 @@ def main():
                 for c in copies:
                     gph = torch.cuda.CUDAGraph()
                     with torch.cuda.graph(gph, stream=side):
-                        stream = torch.cuda.current_stream()
                         step(c, lf=lf)
                     gs.append(gph)
                 graph_sets.append(gs)
@@ -320,7 +403,7 @@ def main():
 
     # the same step on the compact hit form, timed the same way
     compact = None
-    if not args.no_compact:
+    if full and not args.no_compact:
         gc = None
         if graphs is not None:
             gc = []
@@ -347,12 +430,13 @@ def main():
             raise RuntimeError(f"device error flags {int(flags.item())}")
         cms = c0.elapsed_time(c1) / K
         compact = {"events_per_s": round(E / (cms * 1e-3), 1), "ms_per_step": round(cms, 5),
-                   "what": "the same step with the decoder writing lhcbid/u/weight only (12 B per hit) "
-                           "and the search taking the detector's y range for every strip"}
+                   "what": "the same step on one stream with the decoder writing lhcbid/u/weight only "
+                           "(12 B per hit) and the search taking the detector's y range for every strip"}
+        gc = None
 
     # the same decode + Compass work launched one event at a time (eager), for comparison
     per_event = None
-    if not args.no_per_event:
+    if full and not args.no_per_event:
         c = copies[0]
         host_ho = c["hits"]["hit_offsets"].cpu().numpy().view(np.uint32).copy()
         hits2 = {k: torch.empty_like(v) for k, v in c["hits"].items() if k != "error_flags"}
@@ -367,8 +451,12 @@ def main():
         pe1.record(stream)
         torch.cuda.synchronize()
         pe_ms = pe0.elapsed_time(pe1)
+        batched_ms = float(call_ms[0] + call_ms[1])
         per_event = {"events_per_s": round(E / (pe_ms * 1e-3), 1), "ms": round(pe_ms, 3),
-                     "what": "ut_decode + compass_find, one event per call, eager launches"}
+                     "batched_decode_compass_events_per_s": round(E / (batched_ms * 1e-3), 1),
+                     "what": "ut_decode + compass_find, one event per call, eager launches, against "
+                             "the same two calls over the whole batch (eager, one stream)"}
+        hits2 = res2 = scratch = None
 
     # algorithmic bytes (each input read once, each output written once)
     Nw, Nh, Nt = b.n_words, n_valid, b.n_tracks
@@ -378,58 +466,30 @@ def main():
     bytes_fg = Nt * (16 + 16 + 4 + 8) + fg_hits * 12 + 2 * 4 * (4 * S)
     bytes_step = 2 * Nw + 8 * NB + 24 * Nh + 44 * Nt
     names = ["ut_decode", "compass_find", "compass_fit_grad"]
-    per_call_bytes = [bytes_decode, bytes_find, bytes_fg]
-    dom = int(np.argmax(call_ms))
+    per_call_bytes = dict(zip(names, [bytes_decode, bytes_find, bytes_fg]))
+    calls = {n: float(m) for n, m in zip(names, call_ms)}
+    dom = names[int(np.argmax(call_ms))]
     shape_tags = {"k_decode": launch_tag(lau_dec, 4 * E, (lau_dec or {}).get("block", 64) // 64),
                   "k_compass": launch_tag(lau_find, E)}
-    lau_dom = shape_tags.get(KERNEL_OF_CALL[names[dom]])
-    achieved = per_call_bytes[dom] / (call_ms[dom] * 1e-3) / 1e9
-    value = E / (ms_per_step * 1e-3)
-    copy_bw = None if args.no_copy_bandwidth else copy_bandwidth()
-
-    out = {
-        "metric": "events/s UT decode+Compass @1 GPU (HBM GB/s); fwd+bwd fitted tracks/s",
-        "value": round(value, 1),
-        "unit": "events/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {E} events, {S} sectors/layer, {Nt} VELO tracks, "
-                               f"{Nh} hits, {Nw} raw words",
-                   "step": "ut_decode + compass_find + compass_fit_grad(fwd+bwd)",
-                   "rotated_copies": R, "streams": NS, "search_launch_timed": find_choices[GI],
-                   "stream_trials_ms_per_step": stream_trials},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_OF_CALL[names[dom]], "call": names[dom],
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(KERNEL_OF_CALL[names[dom]], args.workload, lau_dom),
-                     "copy_GBps": round(copy_bw, 1) if copy_bw else None,
-                     "frac_of_copy": round(achieved / copy_bw, 4) if copy_bw else None,
-                     "valu_issue": valu_issue(KERNEL_OF_CALL[names[dom]], args.workload, call_ms[dom],
-                                              lau_dom)},
-        "calls_ms": {n: round(float(m), 5) for n, m in zip(names, call_ms)},
-        "step_algorithmic_GBps": round(bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
-        "decode_GBps": round(bytes_decode / (call_ms[0] * 1e-3) / 1e9, 1),
-        "timing": "hip graph replay" if graphs is not None else "eager launches",
+    select = bench_select(args, b, geom, copies[0], E, S) if full else None
+    timing = "hip graph replay" if graph_sets is not None else "eager launches"
+    copies = graph_sets = graphs = None
+    return {
+        "batch": b, "E": E, "S": S, "Nt": Nt,
+        "workload": f"{workload}: {E} events, {S} sectors/layer, {Nt} VELO tracks, {Nh} hits, "
+                    f"{Nw} raw words",
+        "value": E / (ms_per_step * 1e-3), "ms_per_step": ms_per_step, "wall_s": wall,
+        "rotated_copies": R, "streams": NS, "search_launch_timed": find_choices[GI],
+        "stream_trials": stream_trials, "calls_ms": calls, "dominant": dom,
+        "per_call_GBps": {n: per_call_bytes[n] / (calls[n] * 1e-3) / 1e9 for n in names},
+        "step_GBps": bytes_step / (ms_per_step * 1e-3) / 1e9,
+        "shape_tags": shape_tags,
+        "timing": timing,
         "launch": {"decode": lau_dec, "find": lau_find, "source": "autotuner" if tuned else "defaults",
                    "shape_tags": shape_tags},
-        "batched_vs_per_event": per_event,
-        "compact_hits": compact,
-        "found_fraction": round(n_found / max(Nt, 1), 5),
-        "wall_s": round(wall, 4),
+        "per_event": per_event, "compact": compact, "found_fraction": n_found / max(Nt, 1),
+        "select": select,
     }
-    out["event_cut_and_consolidation"] = bench_select(args, b, geom, copies[0], E, S)
-    if not args.no_fitgrad:
-        out["fitgrad"] = bench_fitgrad(args, dev)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
 
 
 def bench_select(args, b, geom, c, E, S):
@@ -589,30 +649,39 @@ def bench_fitgrad(args, dev):
     off = torch.zeros(4 * S, dtype=torch.float32, device=dev)
     n = int(qop.shape[0])
     ws = torch.empty(utc.library().compass_fit_grad_workspace_bytes(S), dtype=torch.uint8, device=dev)
-    out = dict(chi2_total=torch.empty(1, dtype=torch.float64, device=dev),
-               chi2_track=torch.empty(n, dtype=torch.float32, device=dev),
-               grad_qop=torch.empty(n, dtype=torch.float32, device=dev),
-               grad_offsets=torch.empty(4 * S, dtype=torch.float32, device=dev))
-    fwd_out = dict(chi2_total=out["chi2_total"], chi2_track=out["chi2_track"])
+    # copies of every input and output used in turn, so that one call's working set (~95 MB) is not
+    # still in the 256 MB Infinity Cache when the next call with the same copy starts
+    R = max(3, args.rotate)
+    copies = []
+    for _ in range(R):
+        o = dict(chi2_total=torch.empty(1, dtype=torch.float64, device=dev),
+                 chi2_track=torch.empty(n, dtype=torch.float32, device=dev),
+                 grad_qop=torch.empty(n, dtype=torch.float32, device=dev),
+                 grad_offsets=torch.empty(4 * S, dtype=torch.float32, device=dev))
+        copies.append(dict(idx=idx.clone(), st=[v.clone() for v in st], qop=qop.clone(),
+                           u=hits["u"].clone(), w=hits["weight"].clone(), id=hits["lhcbid"].clone(),
+                           off=off.clone(), out=o,
+                           fwd=dict(chi2_total=o["chi2_total"], chi2_track=o["chi2_track"])))
 
-    def call(o, grad):
-        utc.compass_fit_grad(geom, idx, hits["u"], hits["weight"], hits["lhcbid"], *st, qop, off,
-                             want_grad=grad, out=o, workspace=ws)
+    def call(c, grad):
+        utc.compass_fit_grad(geom, c["idx"], c["u"], c["w"], c["id"], *c["st"], c["qop"], c["off"],
+                             want_grad=grad, out=c["out"] if grad else c["fwd"], workspace=ws)
 
     def timed(fn, reps):
-        for _ in range(args.warmup):
-            fn()
+        for i in range(args.warmup):
+            fn(i)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        for _ in range(reps):
-            fn()
+        for i in range(reps):
+            fn(i)
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    ms_fb = timed(lambda: call(out, True), args.steps)
-    ms_f = timed(lambda: call(fwd_out, False), args.steps)
+    ms_fb = timed(lambda i: call(copies[i % R], True), args.steps)
+    ms_f = timed(lambda i: call(copies[i % R], False), args.steps)
+    out = copies[0]["out"]
     # the same work, one call per event
     ev_of_track = np.repeat(np.arange(b.n_events), np.diff(b.velo_offsets.astype(np.int64)))
     kept_per_event = np.bincount(ev_of_track[keep.cpu().numpy()], minlength=b.n_events)
@@ -627,23 +696,54 @@ def bench_fitgrad(args, dev):
             utc.compass_fit_grad(geom, idx[t0:t1], hits["u"], hits["weight"], hits["lhcbid"],
                                  *(v[t0:t1] for v in st), qop[t0:t1], off, out=o, workspace=ws)
 
-    ms_pe = timed(per_event, 1) if not args.no_per_event else None
+    ms_pe = timed(lambda i: per_event(), 1) if not args.no_per_event else None
     n_hits = int((idx >= 0).sum().item())
     bytes_fb = n * (16 + 16 + 4 + 8) + n_hits * 12 + 2 * 4 * (4 * S)
     return {"workload": f"fitgrad: {b.n_events} events, {n} frozen tracks, {n_hits} hits, {S} sectors/layer",
             "fwd_bwd_tracks_per_s": round(n / (ms_fb * 1e-3), 1), "fwd_bwd_ms": round(ms_fb, 5),
             "fwd_only_tracks_per_s": round(n / (ms_f * 1e-3), 1), "fwd_only_ms": round(ms_f, 5),
             "fwd_bwd_algorithmic_GBps": round(bytes_fb / (ms_fb * 1e-3) / 1e9, 1),
+            "rotated_copies": R,
             "per_event_launch_tracks_per_s": round(n / (ms_pe * 1e-3), 1) if ms_pe else None,
             "per_event_launch_ms": round(ms_pe, 3) if ms_pe else None,
             "per_event_what": "compass_fit_grad fwd+bwd, one call per event (the offset gradient of "
                               "each call overwrites the last; no cross-event sum)"}
 
 
-def cpu_baseline(b, seconds):
-    """The oracle (single thread) on a bounded sample of the same events: the first m events, m
-    chosen so that one pass takes about a second, passes repeated until about `seconds` elapse."""
+def host_cpu_info():
+    """What the host offers this process: logical CPUs, the affinity set, the cgroup CPU quota
+    (cpu.max, in CPUs) and the CPU model."""
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cgroup_cpus": None,
+            "model": None}
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            info["cgroup_cpus"] = round(int(q) / int(per), 2)
+    except (OSError, ValueError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return info
+
+
+# CPUs a one-GPU job may keep busy on the GPU host (its share of the host), whatever the host
+# reports as online
+HOST_CPU_SHARE = 16
+
+
+def cpu_baseline(b, seconds, n_events=2000):
+    """The oracle (decode + Compass + fit-chi2 fwd+bwd) on a bounded sample of the same workload:
+    the first `n_events` events.  Timed on every CPU of this process's host share (events are
+    independent, so the sample is split into one slice per thread; the oracle's C calls release
+    the interpreter lock), and on one thread.  Events/s of the sample stand for the whole batch."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     import synth
 
@@ -655,31 +755,13 @@ def cpu_baseline(b, seconds):
                         sub.velo_y, sub.velo_tx, sub.velo_ty, c["qop"],
                         np.zeros(4 * sub.detector.n_sectors, np.float32))
 
-    m = min(b.n_events, 20)
-    while True:
-        sub = synth.take_events(b, np.arange(m)) if m < b.n_events else b
-        t0 = time.perf_counter()
-        one_pass(sub)
-        dt = time.perf_counter() - t0
-        if m == b.n_events or dt >= 0.5:
-            break
-        m = min(b.n_events, max(m + 1, int(m * 1.0 / max(dt, 1e-3))))
-    reps, t = 1, dt
-    t0 = time.perf_counter() - dt
-    while t < seconds:
-        one_pass(sub)
-        reps += 1
-        t = time.perf_counter() - t0
-    out = {"value": round(reps * sub.n_events / t, 1), "unit": "events/s", "cores": 1,
-           "kind": "oracle",
-           "sample": f"{reps} passes over the first {sub.n_events} of the {b.n_events} events "
-                     f"(decode + Compass + fit-chi2 fwd+bwd), single thread, {t:.1f} s"}
-
-    # the same oracle on every host core given to this process: events are independent, so the
-    # sample is split into one slice per thread (the oracle's C calls release the interpreter lock)
-    import os
-    from concurrent.futures import ThreadPoolExecutor
-    cores = max(1, min(16, len(os.sched_getaffinity(0)), sub.n_events))
+    info = host_cpu_info()
+    m = min(b.n_events, n_events)
+    sub = synth.take_events(b, np.arange(m)) if m < b.n_events else b
+    share = [info["affinity"], HOST_CPU_SHARE]
+    if info["cgroup_cpus"]:
+        share.append(int(info["cgroup_cpus"]))
+    cores = max(1, min(*share, sub.n_events))
     cuts = np.linspace(0, sub.n_events, cores + 1).astype(np.int64)
     slices = [synth.take_events(sub, np.arange(cuts[i], cuts[i + 1])) for i in range(cores)]
     budget = seconds / 2
@@ -695,11 +777,26 @@ def cpu_baseline(b, seconds):
     t1 = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
         done = sum(ex.map(worker, slices))
-    t = time.perf_counter() - t1
-    out["all_cores"] = {"value": round(done / t, 1), "unit": "events/s", "cores": cores,
-                        "sample": f"the same {sub.n_events} events split over {cores} threads, each "
-                                  f"repeating its slice for {budget:.0f} s ({t:.1f} s wall)"}
-    return out
+    t_all = time.perf_counter() - t1
+    value = done / t_all
+
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        one_pass(sub)
+        reps += 1
+        t_one = time.perf_counter() - t0
+        if t_one >= budget:
+            break
+    one = reps * sub.n_events / t_one
+    return {"value": round(value, 1), "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": f"the first {sub.n_events} of the {b.n_events} events (decode + Compass + "
+                      f"fit-chi2 fwd+bwd), split over {cores} threads, each repeating its slice for "
+                      f"{budget:.0f} s ({t_all:.1f} s wall); the rate stands for the whole batch "
+                      f"({b.n_events / value:.1f} s extrapolated)",
+            "host": info, "host_share_cpus": HOST_CPU_SHARE,
+            "single_thread": {"value": round(one, 1), "unit": "events/s", "cores": 1,
+                              "sample": f"{reps} passes over the same {sub.n_events} events, "
+                                        f"{t_one:.1f} s"}}
 
 
 if __name__ == "__main__":

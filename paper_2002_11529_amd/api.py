@@ -296,11 +296,24 @@ def compass_fit_grad(geom: Geometry, track_hit_idx, hit_u, hit_weight, hit_lhcbi
     return out
 
 
+def _fit_grad_workspace(geom: Geometry, device):
+    """One fit-gradient workspace per geometry and device, kept on the Geometry object and reused by
+    every call made through CompassChi2Function (calls on one stream only; the workspace is
+    scratch of a single call)."""
+    cache = geom.__dict__.setdefault("_fit_grad_ws", {})
+    key = str(torch.device(device))
+    if key not in cache:
+        cache[key] = _workspace(library().compass_fit_grad_workspace_bytes(geom.n_sectors), device)
+    return cache[key]
+
+
 class CompassChi2Function(torch.autograd.Function):
     """chi2_total(qop, offsets) of frozen track fits, with the library's hand-written adjoint.
 
     Usage: chi2 = CompassChi2Function.apply(qop, offsets, geom, frozen) where `frozen` is a dict of
-    device tensors track_hit_idx, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty.
+    device tensors track_hit_idx, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty.  The forward and
+    backward calls share one workspace per geometry and device, so calls on several streams at once
+    must not use one Geometry.
     """
 
     @staticmethod
@@ -308,7 +321,8 @@ class CompassChi2Function(torch.autograd.Function):
         r = compass_fit_grad(geom, frozen["track_hit_idx"], frozen["hit_u"], frozen["hit_weight"],
                              frozen["hit_lhcbid"], frozen["vx"], frozen["vy"], frozen["vtx"],
                              frozen["vty"], qop.detach().contiguous(), offsets.detach().contiguous(),
-                             want_grad=False, want_chi2_track=False)
+                             want_grad=False, want_chi2_track=False,
+                             workspace=_fit_grad_workspace(geom, qop.device))
         ctx.save_for_backward(qop, offsets)
         ctx.geom, ctx.frozen = geom, frozen
         return r["chi2_total"][0]
@@ -320,7 +334,8 @@ class CompassChi2Function(torch.autograd.Function):
         r = compass_fit_grad(ctx.geom, f["track_hit_idx"], f["hit_u"], f["hit_weight"],
                              f["hit_lhcbid"], f["vx"], f["vy"], f["vtx"], f["vty"],
                              qop.detach().contiguous(), offsets.detach().contiguous(),
-                             grad_scale=1.0, want_grad=True, want_chi2_track=False)
+                             grad_scale=1.0, want_grad=True, want_chi2_track=False,
+                             workspace=_fit_grad_workspace(ctx.geom, qop.device))
         g = grad_out.to(torch.float32)
         return r["grad_qop"] * g, r["grad_offsets"] * g, None, None
 

@@ -2,9 +2,9 @@
 
 * realistic: 1000 events (200 sectors): every decoded hit and every track against the oracle.
 * batched: 20000 uneven events (32 sectors): every decoded hit and every track against the oracle.
-* pileup: 10000 high-occupancy events (200 sectors, 16-hit windows): every output of 600 sampled
-  events (seeded, plus the largest and the smallest event) against the oracle run on those events
-  alone, and properties that hold for every event.
+* pileup: 10000 high-occupancy events (200 sectors, 16-hit windows): every decoded hit, every track
+  and the fraction of VELO tracks with a candidate against the oracle, run on event slices over the
+  host's CPUs.
 * fitgrad: 21000 events, about 1.05 million frozen tracks: chi2 and gradients of all of them against
   the float32 oracle and the binary64 reference.
 """
@@ -95,38 +95,58 @@ def test_batched_full_every_output():
     assert np.array_equal(_u32(res["chi2"]), c["chi2"].view(np.uint32))
 
 
-def test_pileup_full_sampled_events():
+def _oracle_slices(b, threads):
+    """The oracle on contiguous event slices of `b`, one thread per slice (events are independent;
+    the oracle's C calls release the interpreter lock).  Returns [(first event, end event, decoded
+    hits, tracks)] with hit offsets and indices local to the slice."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    n = max(1, min(threads, len(os.sched_getaffinity(0)), b.n_events))
+    cuts = np.linspace(0, b.n_events, n + 1).astype(np.int64)
+
+    def run(k):
+        sub = synth.take_events(b, np.arange(cuts[k], cuts[k + 1]))
+        d = oracle.decode(sub.detector, sub.words, sub.bank_offsets, sub.n_events,
+                          hit_capacity=sub.n_words)
+        c = oracle.compass(sub.detector, sub.params, sub.n_events, d, sub.velo_x, sub.velo_y,
+                           sub.velo_tx, sub.velo_ty, sub.velo_offsets)
+        return int(cuts[k]), int(cuts[k + 1]), d, c
+
+    with ThreadPoolExecutor(n) as ex:
+        return list(ex.map(run, range(n)))
+
+
+def test_pileup_full_every_output():
+    """All 10000 pile-up events: every decoded hit, every track output and the fraction of VELO
+    tracks with a candidate, against the oracle (run on event slices over the host's CPUs)."""
     b = synth.generate("pileup", with_truth=False)
     geom, dv, hits, res = _run_tuned(b)
     nh = _common_properties(b, hits, res)
     S = b.detector.n_sectors
     nb = L * S
-    tpe = np.diff(b.velo_offsets.astype(np.int64))
-    rng = np.random.default_rng(2024)
-    sample = np.unique(np.concatenate([rng.choice(b.n_events, 600, replace=False),
-                                       [int(np.argmax(tpe)), int(np.argmin(tpe)), b.n_events - 1]]))
-    sub = synth.take_events(b, sample)
-    d = oracle.decode(sub.detector, sub.words, sub.bank_offsets, sub.n_events, hit_capacity=sub.n_words)
-    c = oracle.compass(sub.detector, sub.params, sub.n_events, d, sub.velo_x, sub.velo_y, sub.velo_tx,
-                       sub.velo_ty, sub.velo_offsets)
-    ho = hits["hit_offsets"]
+    ho = _u32(hits["hit_offsets"]).astype(np.int64)
+    n = int(ho[-1])
+    h = {f: _u32(hits[f][:n]) for f in ("lhcbid", "u", "weight", "z", "y_begin", "y_end")}
+    gi_all = res["hit_idx"].cpu().numpy().astype(np.int64)
+    q_all, c2_all = _u32(res["qop"]), _u32(res["chi2"])
     vo = b.velo_offsets.astype(np.int64)
-    for k, e in enumerate(sample):
-        g_off = _u32(ho[e * nb:(e + 1) * nb + 1]).astype(np.int64)
-        o_off = d["hit_offsets"][k * nb:(k + 1) * nb + 1].astype(np.int64)
-        assert np.array_equal(g_off - g_off[0], o_off - o_off[0]), e
-        g0, g1, o0 = int(g_off[0]), int(g_off[-1]), int(o_off[0])
-        for f in ("lhcbid", "u", "weight", "z", "y_begin", "y_end"):
-            assert np.array_equal(_u32(hits[f][g0:g1]), d[f][o0:o0 + g1 - g0].view(np.uint32)), (e, f)
-        t0, t1 = vo[e], vo[e + 1]
-        c0, c1 = int(sub.velo_offsets[k]), int(sub.velo_offsets[k + 1])
-        gi = res["hit_idx"][t0:t1].cpu().numpy().astype(np.int64)
-        oi = c["hit_idx"][c0:c1].astype(np.int64)
-        assert np.array_equal(np.where(gi >= 0, gi - g0, -1), np.where(oi >= 0, oi - o0, -1)), e
-        assert np.array_equal(nh[t0:t1], c["nhits"][c0:c1]), e
-        assert np.array_equal(_u32(res["qop"][t0:t1]), c["qop"][c0:c1].view(np.uint32)), e
-        assert np.array_equal(_u32(res["chi2"][t0:t1]), c["chi2"][c0:c1].view(np.uint32)), e
-    print(f"[pileup full] found fraction {float((nh > 0).mean()):.4f}", flush=True)
+    found_oracle = 0
+    for e0, e1, d, c in _oracle_slices(b, 16):
+        g0, g1 = int(ho[e0 * nb]), int(ho[e1 * nb])
+        assert np.array_equal(ho[e0 * nb:e1 * nb + 1] - g0, d["hit_offsets"].astype(np.int64)), (e0, e1)
+        for f in h:
+            assert np.array_equal(h[f][g0:g1], d[f][:g1 - g0].view(np.uint32)), (e0, f)
+        t0, t1 = vo[e0], vo[e1]
+        oi = c["hit_idx"].astype(np.int64)
+        assert np.array_equal(gi_all[t0:t1], np.where(oi >= 0, oi + g0, -1)), e0
+        assert np.array_equal(nh[t0:t1], c["nhits"]), e0
+        assert np.array_equal(q_all[t0:t1], c["qop"].view(np.uint32)), e0
+        assert np.array_equal(c2_all[t0:t1], c["chi2"].view(np.uint32)), e0
+        found_oracle += int((c["nhits"] > 0).sum())
+    found_gpu = int((nh > 0).sum())
+    assert found_gpu == found_oracle
+    print(f"[pileup full] found fraction {found_gpu / b.n_tracks:.5f} (GPU) = "
+          f"{found_oracle / b.n_tracks:.5f} (oracle), {b.n_tracks} VELO tracks", flush=True)
 
 
 def test_fitgrad_full_million_tracks():
