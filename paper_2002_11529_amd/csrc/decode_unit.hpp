@@ -240,6 +240,58 @@ __device__ inline uint32_t count_below(const uint32_t* k, uint32_t mine) {
   return r;
 }
 
+// Banks of more than kDenseBank hits are ordered by a counting sort on the top 6 bits of the word
+// (8-strip bins) followed by a rank among the few hits of the same bin, instead of a rank against
+// the whole bank: O(n) rather than O(n^2) per bank.
+constexpr uint32_t kDenseBank = 32;
+constexpr int kBins = 64;
+
+// Hits [lo, hi) of the chunk (compacted order, keys word << 16 | position in ws.key), all of bank
+// `bank`: decoded and stored at first + their rank in the bank by key.  The chunk's staged raw
+// words, its marker array and the bank entries of these hits are no longer needed at this point
+// and serve as bin counters, arrival slots and the bin-ordered hit list.  Wave-uniform.
+__device__ inline void dense_bank(const Geom& g, int layer, int bank, uint32_t lo, uint32_t hi,
+                                  const WaveScratch& ws, float z_l, int64_t first, int64_t capacity,
+                                  const HitsOut& out, uint32_t* flags)
+{
+  const int lane = lane_id();
+  uint32_t* bins = reinterpret_cast<uint32_t*>(ws.raw);   // [kBins + 1]
+  uint16_t* slot = ws.mark;                               // [k] arrival slot of hit k in its bin
+  uint16_t* order = ws.cbank;                             // [lo + i] i-th hit in bin order
+  bins[lane] = 0u;
+  if (lane == 0) bins[kBins] = 0u;
+  wave_sync();
+  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
+    slot[k] = (uint16_t)atomicAdd(&bins[ws.key[k] >> 26], 1u);
+  wave_sync();
+  uint32_t tot;
+  const uint32_t start = wave_excl_scan(bins[lane], &tot);
+  wave_sync();
+  bins[lane] = start;
+  if (lane == 0) bins[kBins] = tot;
+  wave_sync();
+  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
+    order[lo + bins[ws.key[k] >> 26] + slot[k]] = (uint16_t)k;
+  wave_sync();
+  const float u0 = ws.u0[bank];
+  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave) {
+    const uint32_t mine = ws.key[k];
+    const uint32_t v = mine >> 16;
+    const float w = ws.wt[v & 0xFu];
+    const uint32_t bin = mine >> 26;
+    const uint32_t s1 = bins[bin + 1];
+    uint32_t rank = bins[bin];   // hits of the lower bins
+    for (uint32_t j = bins[bin]; j < s1; ++j) rank += ws.key[order[lo + j]] < mine;
+    const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
+    DecodedHit d;
+    d.lhcbid = ((uint32_t)layer << 28) | ((uint32_t)bank << 12) | (strip << 3) | frac;
+    d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0);
+    d.w = w;
+    store_hit(g, z_l, d, first + lo + rank, capacity, out, flags);
+  }
+  wave_sync();
+}
+
 // Compaction, sort and store of the unit's hits, first hit `base`.
 __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ words, int layer,
                                   int64_t b0, uint32_t base, const UnitCount& st,
@@ -352,15 +404,17 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
 
     // each hit's rank in its bank by (word, position): sorted by word value, ties in bank order;
     // the hit is decoded and stored straight to its sorted slot (the 64 lanes cover a contiguous
-    // range of the output, permuted inside each bank)
+    // range of the output, permuted inside each bank).  Banks of more than kDenseBank hits are
+    // ranked afterwards by dense_bank.
     for (uint32_t k = lane; k < nh; k += kWave) {
       const int bk = ws.cbank[k];
+      const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
+      if (hi - lo > kDenseBank) continue;
       const uint32_t mine = ws.key[k];
       const uint32_t v = mine >> 16;
       // table lookups first, so that their latency overlaps the rank loop
       const float u0 = ws.u0[bk];
       const float w = ws.wt[v & 0xFu];
-      const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
       // keys of the bank below this hit's, compared 16, 8 and 4 at a time (independent LDS reads
       // in flight; the central banks of an event hold tens of hits), then the last up to three
       uint32_t rank = 0;
@@ -384,6 +438,18 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0);
       d.w = w;
       store_hit(g, z_l, d, (int64_t)base + local + slot, capacity, out, flags);
+    }
+    wave_sync();
+    // the dense banks of the chunk, one after the other (found 64 banks at a time by a ballot)
+    for (int b0c = c0; b0c < c1; b0c += kWave) {
+      const int b = b0c + lane;
+      uint64_t dense = ballot(b < c1 && ws.hb[b + 1] - ws.hb[b] > kDenseBank);
+      while (dense) {
+        const int bd = b0c + (int)__builtin_ctzll(dense);
+        dense &= dense - 1;
+        dense_bank(g, layer, bd, ws.hb[bd], ws.hb[bd + 1], ws, z_l, (int64_t)base + local, capacity,
+                   out, flags);
+      }
     }
     local += nh;
     c0 = c1;
