@@ -25,15 +25,19 @@ struct WaveScratch {
   uint32_t* hb;     // [S+1] first hit of each bank inside the current chunk
   float* u0;        // [S] bin-0 position of each sector of the unit's layer
   float* wt;        // [16] weight of each cluster size
-  uint16_t* raw;    // [cap] staged raw words
+  uint32_t* bins;   // [kBins+1] bin counters / starts of the dense-bank sort
+  uint16_t* raw;    // [cap] staged raw words, then the chunk's words in sorted order
   uint32_t* key;
   uint16_t* cbank;  // [cap] bank of each valid word in bank order
   uint16_t* mark;   // [cap] bank start markers by raw position, then valid words before it
   int cap;
 };
 
+constexpr int kBins = 64;   // bins of the dense-bank sort: the top 6 bits of the word (8 strips)
+
 __host__ __device__ inline size_t wave_table_bytes(int S) {
-  return 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(float) * ((size_t)S + 16);
+  return 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(float) * ((size_t)S + 16) +
+         sizeof(uint32_t) * (kBins + 4);
 }
 
 __host__ __device__ inline size_t wave_scratch_bytes(int S, int cap) {
@@ -55,7 +59,8 @@ __device__ inline WaveScratch carve_scratch(char* p, int S, int cap) {
   w.hb = w.off + (S + 1);
   w.u0 = reinterpret_cast<float*>(w.hb + (S + 1));
   w.wt = w.u0 + S;
-  w.key = reinterpret_cast<uint32_t*>(w.wt + 16);
+  w.bins = reinterpret_cast<uint32_t*>(w.wt + 16);
+  w.key = w.bins + kBins + 4;
   w.raw = reinterpret_cast<uint16_t*>(w.key + cap);
   w.cbank = w.raw + cap;
   w.mark = w.cbank + cap;
@@ -244,20 +249,17 @@ __device__ inline uint32_t count_below(const uint32_t* k, uint32_t mine) {
 // (8-strip bins) followed by a rank among the few hits of the same bin, instead of a rank against
 // the whole bank: O(n) rather than O(n^2) per bank.
 constexpr uint32_t kDenseBank = 32;
-constexpr int kBins = 64;
 
-// Hits [lo, hi) of the chunk (compacted order, keys word << 16 | position in ws.key), all of bank
-// `bank`: decoded and stored at first + their rank in the bank by key.  The chunk's staged raw
-// words, its marker array and the bank entries of these hits are no longer needed at this point
-// and serve as bin counters, arrival slots and the bin-ordered hit list.  Wave-uniform.
-__device__ inline void dense_bank(const Geom& g, int layer, int bank, uint32_t lo, uint32_t hi,
-                                  const WaveScratch& ws, float z_l, int64_t first, int64_t capacity,
-                                  const HitsOut& out, uint32_t* flags)
+// Hits [lo, hi) of the chunk (compacted order, keys word << 16 | position in ws.key), all of one
+// bank: each word goes to sorted[lo + its rank in the bank by key].  The chunk's marker array and
+// the bank entries of these hits are no longer needed at this point and serve as arrival slots and
+// the bin-ordered hit list.  Wave-uniform.
+__device__ inline void dense_bank(uint32_t lo, uint32_t hi, const WaveScratch& ws, uint16_t* sorted)
 {
   const int lane = lane_id();
-  uint32_t* bins = reinterpret_cast<uint32_t*>(ws.raw);   // [kBins + 1]
-  uint16_t* slot = ws.mark;                               // [k] arrival slot of hit k in its bin
-  uint16_t* order = ws.cbank;                             // [lo + i] i-th hit in bin order
+  uint32_t* bins = ws.bins;      // [kBins + 1]
+  uint16_t* slot = ws.mark;      // [k] arrival slot of hit k in its bin
+  uint16_t* order = ws.cbank;    // [lo + i] i-th hit in bin order
   bins[lane] = 0u;
   if (lane == 0) bins[kBins] = 0u;
   wave_sync();
@@ -273,21 +275,13 @@ __device__ inline void dense_bank(const Geom& g, int layer, int bank, uint32_t l
   for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
     order[lo + bins[ws.key[k] >> 26] + slot[k]] = (uint16_t)k;
   wave_sync();
-  const float u0 = ws.u0[bank];
   for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave) {
     const uint32_t mine = ws.key[k];
-    const uint32_t v = mine >> 16;
-    const float w = ws.wt[v & 0xFu];
     const uint32_t bin = mine >> 26;
     const uint32_t s1 = bins[bin + 1];
     uint32_t rank = bins[bin];   // hits of the lower bins
     for (uint32_t j = bins[bin]; j < s1; ++j) rank += ws.key[order[lo + j]] < mine;
-    const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
-    DecodedHit d;
-    d.lhcbid = ((uint32_t)layer << 28) | ((uint32_t)bank << 12) | (strip << 3) | frac;
-    d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0);
-    d.w = w;
-    store_hit(g, z_l, d, first + lo + rank, capacity, out, flags);
+    sorted[lo + rank] = (uint16_t)(mine >> 16);
   }
   wave_sync();
 }
@@ -403,18 +397,14 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
     for (int b = c0 + lane; b < c1; b += kWave) hit_offsets[b0 + b] = base + local + ws.hb[b];
 
     // each hit's rank in its bank by (word, position): sorted by word value, ties in bank order;
-    // the hit is decoded and stored straight to its sorted slot (the 64 lanes cover a contiguous
-    // range of the output, permuted inside each bank).  Banks of more than kDenseBank hits are
-    // ranked afterwards by dense_bank.
+    // the word goes to its sorted slot of the chunk in LDS (the staged raw words are no longer
+    // needed).  Banks of more than kDenseBank hits are ranked afterwards by dense_bank.
+    uint16_t* sorted = ws.raw;
     for (uint32_t k = lane; k < nh; k += kWave) {
       const int bk = ws.cbank[k];
       const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
       if (hi - lo > kDenseBank) continue;
       const uint32_t mine = ws.key[k];
-      const uint32_t v = mine >> 16;
-      // table lookups first, so that their latency overlaps the rank loop
-      const float u0 = ws.u0[bk];
-      const float w = ws.wt[v & 0xFu];
       // keys of the bank below this hit's, compared 16, 8 and 4 at a time (independent LDS reads
       // in flight; the central banks of an event hold tens of hits), then the last up to three
       uint32_t rank = 0;
@@ -431,13 +421,7 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       if (j < hi) rank += ws.key[j] < mine;
       if (j + 1 < hi) rank += ws.key[j + 1] < mine;
       if (j + 2 < hi) rank += ws.key[j + 2] < mine;
-      const uint32_t slot = lo + rank;
-      const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
-      DecodedHit d;
-      d.lhcbid = ((uint32_t)layer << 28) | ((uint32_t)bk << 12) | (strip << 3) | frac;
-      d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0);
-      d.w = w;
-      store_hit(g, z_l, d, (int64_t)base + local + slot, capacity, out, flags);
+      sorted[lo + rank] = (uint16_t)(mine >> 16);
     }
     wave_sync();
     // the dense banks of the chunk, one after the other (found 64 banks at a time by a ballot)
@@ -447,8 +431,32 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       while (dense) {
         const int bd = b0c + (int)__builtin_ctzll(dense);
         dense &= dense - 1;
-        dense_bank(g, layer, bd, ws.hb[bd], ws.hb[bd + 1], ws, z_l, (int64_t)base + local, capacity,
-                   out, flags);
+        dense_bank(ws.hb[bd], ws.hb[bd + 1], ws, sorted);
+      }
+    }
+    // bank of each sorted slot: sorting stays inside the banks, so slot p belongs to the bank b
+    // with hb[b] <= p < hb[b+1] (markers at the banks' first slots, then a running maximum)
+    for (uint32_t i = lane; i < nh; i += kWave) ws.mark[i] = 0;
+    wave_sync();
+    for (int b = c0 + lane; b < c1; b += kWave)
+      if (ws.hb[b + 1] > ws.hb[b]) ws.mark[ws.hb[b]] = (uint16_t)(b + 1);
+    wave_sync();
+    // decode in sorted order and store: the 64 lanes write 64 consecutive hits of each array
+    uint32_t bank_run = 0;
+    for (uint32_t p0 = 0; p0 < nh; p0 += kWave) {
+      const uint32_t p = p0 + (uint32_t)lane;
+      uint32_t bk1 = wave_inclusive_max(p < nh ? (uint32_t)ws.mark[p] : 0u);
+      bk1 = bk1 > bank_run ? bk1 : bank_run;
+      bank_run = (uint32_t)__builtin_amdgcn_readlane((int)bk1, kWave - 1);
+      if (p < nh) {
+        const uint32_t bk = bk1 - 1u;
+        const uint32_t v = sorted[p];
+        const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
+        DecodedHit d;
+        d.lhcbid = ((uint32_t)layer << 28) | (bk << 12) | (strip << 3) | frac;
+        d.u = fmaf((float)(strip * 8u + frac), g.pitch8, ws.u0[bk]);
+        d.w = ws.wt[v & 0xFu];
+        store_hit(g, z_l, d, (int64_t)base + local + p, capacity, out, flags);
       }
     }
     local += nh;
