@@ -62,7 +62,10 @@ def launch_tag(launch, n_items=None, items_per_workgroup=1):
     g = launch["grid"]
     if g == 0 or (n_items is not None and g * items_per_workgroup >= n_items):
         g = "per-item"
-    return f"block={launch['block']} grid={g}"
+    tag = f"block={launch['block']} grid={g}"
+    if "tile" in launch:   # LDS KiB per wavefront (0: the default 10)
+        tag += f" tile={launch['tile'] or 10}"
+    return tag
 
 
 def counter_fields(kernel, workload, what, launch=None):
@@ -330,7 +333,7 @@ def measure_chain(args, workload, full):
     # for the steps on other streams
     find_choices = [lau_find]
     if lau_find and 0 < lau_find["grid"] < E:
-        find_choices.append({"block": 256, "grid": 0})
+        find_choices.append({"block": 256, "grid": 0, "tile": lau_find.get("tile", 0)})
 
     # the step captured once per buffer copy (and search shape) in a HIP graph, replayed
     graph_sets = None

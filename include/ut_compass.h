@@ -69,20 +69,26 @@ typedef struct {
   float slope_tol;           /* anchor pair accepted if |t_pair - tx_velo| <= slope_tol */
   float completion_tol;      /* completion interval margin (mm) */
   int32_t max_tracklets;     /* 0: minimum over every compatible combination; N > 0: the search of
-                                Section V-B as the paper runs it: per anchor pair the compatible
+                                Section V-B: each window walked central sector first, then its
+                                neighbours at growing distance (left first), ascending x inside a
+                                sector; anchor pairs A-major in that order; per pair the compatible
                                 hit closest to the pair-slope extrapolation in each completion
-                                layer (first on a tie), anchor pairs in window order, stop after
-                                N tracklets */
+                                layer (first in walk order on a tie); stop after N tracklets */
 } utc_compass_params;
 
 /* Launch shape.  NULL selects the defaults.  block: threads per workgroup, a multiple of 64, at
  * most 1024 for ut_decode and 512 for compass_find (a shape outside these limits, or one whose LDS
  * does not fit a CU, is rejected with UTC_ERR_ARG); grid: workgroups (0 = one per work item, > 0 =
- * persistent grid of that many workgroups striding over the work items). */
+ * persistent grid of that many workgroups striding over the work items); window_tile: KiB of LDS
+ * per wavefront for the staged data (ut_decode: the chunk of raw words a wavefront sorts at once;
+ * compass_find: the window cache, i.e. the positions, and when they fit the weights, of the
+ * event's hits that the window searches and the tile read), 0 = 10, else 4 .. 40.  More LDS per
+ * wavefront stages larger events and chunks, less keeps more wavefronts per CU. */
 typedef struct {
   int32_t block;
   int32_t grid;
-  int32_t reserved0, reserved1;
+  int32_t window_tile;
+  int32_t reserved;
 } utc_launch_config;
 
 /* ---------------------------------------------------------------------------------------------
@@ -191,12 +197,14 @@ utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks, const in
 /* ---------------------------------------------------------------------------------------------
  * Autotuning of the batched launch (not in the paper, which tuned its kernel parameters by hand,
  * Section VI-C).  Each call runs the matching entry point on the caller's buffers (same arguments
- * and meaning as ut_decode / compass_find) for every candidate launch shape: block in
- * {64, 128, 256, 512} (decode and Compass), grid in {one workgroup per work
- * item, 256 .. 2048 persistent workgroups}; each shape runs once to warm up and then `reps` times
- * (1..32).  *best receives the first shape, in the order block then grid of the lists above,
- * whose median time is within 2 % of the lowest median (near-equal shapes are within the timing
- * noise; the rule keeps repeated tunings on one shape), *best_us its median in microseconds.
+ * and meaning as ut_decode / compass_find) for every candidate launch shape: window tile in
+ * {10, 6, 16} KiB (decode) or {10, 8, 16, 24} KiB (Compass), block in {64, 128, 256, 512}, grid
+ * in {one workgroup per work item, 512, 2048} (decode) or {one per item, 512, 1024, 2048}
+ * (Compass) persistent workgroups; shapes whose LDS does not fit a CU are skipped.  Each shape
+ * runs once to warm up and then `reps` times (1..32).  *best receives the first shape, in the
+ * order tile, block, grid of the lists above, whose median time is within 2 % of the lowest
+ * median (near-equal shapes are within the timing noise; the rule keeps repeated tunings on one
+ * shape), *best_us its median in microseconds.
  * Results do not depend on the shape.  Unlike the other calls these synchronise
  * the stream (set-up calls); the outputs hold the last run's results.
  * --------------------------------------------------------------------------------------------- */

@@ -43,7 +43,7 @@ class UtcCompassParams(ctypes.Structure):
 
 
 class UtcLaunchConfig(ctypes.Structure):
-    _fields_ = [("block", _i32), ("grid", _i32), ("reserved0", _i32), ("reserved1", _i32)]
+    _fields_ = [("block", _i32), ("grid", _i32), ("window_tile", _i32), ("reserved", _i32)]
 
 
 _lib = None
@@ -133,6 +133,7 @@ def _launch(launch):
     c = UtcLaunchConfig()
     c.block = int(launch.get("block", 256))
     c.grid = int(launch.get("grid", 0))
+    c.window_tile = int(launch.get("tile", 0))
     return ctypes.byref(c)
 
 
@@ -388,7 +389,7 @@ def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy,
     arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
     p = params if isinstance(params, UtcCompassParams) else compass_params(params)
     n_tracks = int(vx.shape[0])
-    key = (f"{arch}|S={geom.n_sectors}|M={p.max_hits}|sec={p.n_sectors_search}|E={n_events}|"
+    key = (f"{arch}|tile|S={geom.n_sectors}|M={p.max_hits}|sec={p.n_sectors_search}|E={n_events}|"
            f"Nw={int(words.shape[0]) >> 16}|Nt={n_tracks >> 10}")
     path = _cache_path()
     cache = {}
@@ -410,7 +411,7 @@ def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy,
                               _ptr(ws), ws.numel(), reps, ctypes.byref(best), ctypes.byref(best_us),
                               _stream(stream))
     _check(st, "ut_decode_autotune")
-    dec = dict(block=best.block, grid=best.grid)
+    dec = dict(block=best.block, grid=best.grid, tile=best.window_tile)
     dec_us = float(best_us.value)
     res = compass_find(geom, p, n_events, hits, vx, vy, vtx, vty, velo_offsets, stream=stream)
     wsf = _workspace(L.compass_find_workspace_bytes(n_events, n_tracks), dev)
@@ -424,7 +425,8 @@ def autotune(geom: Geometry, params, n_events: int, words, bank_offsets, vx, vy,
                                  _ptr(wsf), wsf.numel(), reps, ctypes.byref(best),
                                  ctypes.byref(best_us), _stream(stream))
     _check(st, "compass_find_autotune")
-    out = dict(decode=dec, decode_us=dec_us, find=dict(block=best.block, grid=best.grid),
+    out = dict(decode=dec, decode_us=dec_us,
+               find=dict(block=best.block, grid=best.grid, tile=best.window_tile),
                find_us=float(best_us.value))
     if use_cache:
         cache[key] = out

@@ -1,5 +1,5 @@
-// Launch-shape autotuner for the batched path: times candidate (block, grid) shapes of ut_decode
-// and compass_find on the caller's own buffers with HIP events and keeps the first candidate, in
+// Launch-shape autotuner for the batched path: times candidate (window tile, block, grid) shapes of
+// ut_decode and compass_find on the caller's own buffers with HIP events and keeps the first candidate, in
 // the listed order, within kTieFrac of the fastest (near-equal shapes are within the timing noise;
 // the rule keeps the choice from flipping between them from run to run).  A set-up call: it
 // synchronises the stream, unlike the other entry points.
@@ -43,26 +43,33 @@ float median_us(F&& run, int reps, hipStream_t stream, Timer& tm, bool& ok) {
 
 constexpr float kTieFrac = 0.02f;
 
-// Times every (block, grid) of the two lists with run(config) and picks as described above.
+constexpr int kMaxShapes = 128;
+
+// Times every (window tile, block, grid) of the three lists with run(config) and picks as described
+// above (tiles outermost, so the first tile listed wins a tie).
 template <class F>
-utc_status tune_shapes(const int* blocks, int nb, const int* grids, int ng, F&& run, int reps,
-                       hipStream_t stream, utc_launch_config* best, float* best_us) {
+utc_status tune_shapes(const int* tiles, int nt, const int* blocks, int nb, const int* grids, int ng,
+                       F&& run, int reps, hipStream_t stream, utc_launch_config* best,
+                       float* best_us) {
+  if (nt * nb * ng > kMaxShapes) return UTC_ERR_ARG;
   Timer tm;
-  float t[64];
-  bool okc[64];
+  float t[kMaxShapes];
+  bool okc[kMaxShapes];
+  utc_launch_config cfg[kMaxShapes];
   float t_min = 3.0e38f;
-  for (int i = 0; i < nb; ++i)
-    for (int j = 0; j < ng; ++j) {
-      utc_launch_config c{blocks[i], grids[j], 0, 0};
-      bool ok = false;
-      const int k = i * ng + j;
-      t[k] = median_us([&] { return run(&c); }, reps, stream, tm, ok);
-      okc[k] = ok;
-      if (ok && t[k] < t_min) t_min = t[k];
-    }
-  for (int k = 0; k < nb * ng; ++k)
+  int n = 0;
+  for (int a = 0; a < nt; ++a)
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < ng; ++j, ++n) {
+        cfg[n] = utc_launch_config{blocks[i], grids[j], tiles[a], 0};
+        bool ok = false;
+        t[n] = median_us([&] { return run(&cfg[n]); }, reps, stream, tm, ok);
+        okc[n] = ok;
+        if (ok && t[n] < t_min) t_min = t[n];
+      }
+  for (int k = 0; k < n; ++k)
     if (okc[k] && t[k] <= t_min * (1.0f + kTieFrac)) {
-      *best = utc_launch_config{blocks[k / ng], grids[k % ng], 0, 0};
+      *best = cfg[k];
       *best_us = t[k];
       return UTC_OK;
     }
@@ -81,9 +88,10 @@ extern "C" utc_status ut_decode_autotune(const utc_geometry* geom, const uint16_
                                          hipStream_t stream)
 {
   if (!best || !best_us) return UTC_ERR_ARG;
+  static const int tiles[] = {10, 6, 16};
   static const int blocks[] = {64, 128, 256, 512};
-  static const int grids[] = {0, 256, 512, 1024, 2048};
-  return tune_shapes(blocks, 4, grids, 5, [&](const utc_launch_config* c) {
+  static const int grids[] = {0, 512, 2048};
+  return tune_shapes(tiles, 3, blocks, 4, grids, 3, [&](const utc_launch_config* c) {
     return ut_decode(geom, words, bank_offsets, n_events, hit_capacity, hit_offsets, lhcbid, z, u,
                      y_begin, y_end, weight, error_flags, workspace, workspace_bytes, c, stream);
   }, reps, stream, best, best_us);
@@ -102,9 +110,10 @@ extern "C" utc_status compass_find_autotune(const utc_geometry* geom, const utc_
                                             hipStream_t stream)
 {
   if (!best || !best_us) return UTC_ERR_ARG;
+  static const int tiles[] = {10, 8, 16, 24};
   static const int blocks[] = {64, 128, 256, 512};
   static const int grids[] = {0, 512, 1024, 2048};
-  return tune_shapes(blocks, 4, grids, 4, [&](const utc_launch_config* c) {
+  return tune_shapes(tiles, 4, blocks, 4, grids, 4, [&](const utc_launch_config* c) {
     return compass_find(geom, params, n_events, hit_offsets, hit_u, hit_weight, hit_y_begin, hit_y_end,
                         vx, vy, vtx, vty, velo_offsets, n_tracks, hit_idx, qop, chi2, nhits, nullptr,
                         error_flags, workspace, workspace_bytes, c, stream);

@@ -1,7 +1,7 @@
 // Compass tracking (Section V of the paper) for gfx950: stand-alone kernel over decoded hits.
 //
 // One workgroup per event at a time (events strided over the grid): the event's bank offsets and, when
-// they fit, the u of its hits are staged in LDS; then each wavefront runs the search for groups of
+// they fit, the u (and weights) of its hits are staged in LDS; then each wavefront runs the search for groups of
 // 16 VELO tracks (compass_group.hpp): windows by binary search over the staged hits, tracklets by
 // anchor pairs spread over the lanes, selection by an LDS atomic minimum of a total-order key.
 #include <cmath>
@@ -68,22 +68,27 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     for (int l = 0; l < kLayers; ++l)
       if (s_hoff[(l + 1) * S] - s_hoff[l * S] > 32767u) overflow = true;
     const bool staged = nh <= (uint32_t)u_cap;
+    const bool staged_w = 2 * (uint64_t)nh <= (uint64_t)u_cap;   // the weights too, after the u
     // u of every hit when the event fits, else of every stride-th hit (a coarse index for the
     // window searches, which then finish with a few steps in global memory)
     uint32_t stride = 1;
     while (u_cap > 0 && (nh + stride - 1) / stride > (uint32_t)u_cap) stride *= 2;
     const uint32_t ncoarse = u_cap > 0 ? (nh + stride - 1) / stride : 0u;
     for (uint32_t k0 = 0; k0 < ncoarse; k0 += 8 * bs) {
-      float v[8];
+      float v[8], w[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const uint32_t k = k0 + q * bs + tid;
         v[q] = k < ncoarse ? hu[(int64_t)H + (int64_t)k * stride] : 0.0f;
+        w[q] = (staged_w && k < ncoarse) ? hw[(int64_t)H + k] : 0.0f;
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const uint32_t k = k0 + q * bs + tid;
-        if (k < ncoarse) s_u[k] = v[q];
+        if (k < ncoarse) {
+          s_u[k] = v[q];
+          if (staged_w) s_u[nh + k] = w[q];
+        }
       }
     }
     if (overflow && tid == 0) raise_flag(flags, UTC_FLAG_LAYER_OVERFLOW);
@@ -91,7 +96,7 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     EventView ev;
     ev.u_lds = s_u;
     ev.u_glb = hu;
-    ev.w_lds = nullptr;
+    ev.w_lds = staged_w ? s_u + nh : nullptr;
     ev.w_glb = hw;
     ev.yb_glb = hyb;
     ev.ye_glb = hye;
@@ -106,7 +111,15 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     uint32_t grp = (uint32_t)wid;
     uint32_t nxt = grp < ngroups ? claim_group(s_next) : ngroups;
     LaneState st = load_state(io, t0 + grp * kGroupTracks, t1);
-    if (staged) {
+    if (staged_w) {
+      while (grp < ngroups) {
+        const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
+        compass_group<true, true, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
+        st = next;
+        grp = nxt;
+        nxt = grp < ngroups ? claim_group(s_next) : ngroups;
+      }
+    } else if (staged) {
       while (grp < ngroups) {
         const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
         compass_group<true, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
@@ -177,7 +190,9 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
                        !chi2 || !nhits))
     return UTC_ERR_ARG;
   if ((hit_y_begin == nullptr) != (hit_y_end == nullptr)) return UTC_ERR_ARG;
-  if (launch && (launch->block < 64 || launch->block > 512 || launch->block % 64 || launch->grid < 0))
+  if (launch && (launch->block < 64 || launch->block > 512 || launch->block % 64 || launch->grid < 0 ||
+                 launch->window_tile < 0 || launch->window_tile > 40 ||
+                 (launch->window_tile > 0 && launch->window_tile < 4)))
     return UTC_ERR_ARG;
   if (!workspace || workspace_bytes < compass_find_workspace_bytes(n_events, n_tracks))
     return UTC_ERR_WORKSPACE;
@@ -201,10 +216,12 @@ extern "C" utc_status compass_find(const utc_geometry* geom, const utc_compass_p
   while (!launch && block > kWave && compass_lds_bytes(g.S, p.max_hits, block / kWave, 0, greedy) > 160 * 1024)
     block -= kWave;
   const int waves = block / kWave;
-  // stage u of events up to u_cap hits, keeping the workgroup's LDS at 10 KiB per wavefront (four
-  // 256-thread workgroups share a CU's 160 KiB, the occupancy the kernel's registers allow);
-  // larger events search global memory
-  const size_t budget = (size_t)waves * 10 * 1024;
+  // stage u of events up to u_cap hits (and their weights up to u_cap / 2), keeping the
+  // workgroup's LDS at the window tile per wavefront (by default 10 KiB: four 256-thread workgroups
+  // share a CU's 160 KiB, the occupancy the kernel's registers allow); larger events search
+  // global memory
+  const int tile_kib = (launch && launch->window_tile > 0) ? launch->window_tile : 10;
+  const size_t budget = (size_t)waves * tile_kib * 1024;
   const size_t fixed = compass_lds_bytes(g.S, p.max_hits, waves, 0, greedy);
   const int u_cap = fixed < budget ? (int)((budget - fixed) / sizeof(float)) / 64 * 64 : 0;
   const size_t lds = compass_lds_bytes(g.S, p.max_hits, waves, u_cap, greedy);

@@ -119,7 +119,9 @@ static utc_status decode_launch(const utc_geometry* geom, const uint16_t* words,
   const int n_units = n_events * kLayers;
   uint32_t* unit_base = unit_sum + n_units;
   const Geom g = make_geom(*geom);
-  const int cap = chunk_words(S);
+  const size_t tile = (launch && launch->window_tile > 0) ? (size_t)launch->window_tile * 1024
+                                                          : kWaveLdsDefault;
+  const int cap = chunk_words(S, tile);
   int block = launch ? launch->block : 256;
   while (!launch && block > kWave && (size_t)(block / kWave) * wave_scratch_bytes(S, cap) > 160 * 1024)
     block -= kWave;
@@ -162,7 +164,9 @@ static bool decode_args_ok(const utc_geometry* geom, const uint16_t* words,
       !geom->u0 || n_events < 0 || hit_capacity < 0 || !bank_offsets || !hit_offsets)
     return false;
   if (n_events > 0 && hit_capacity > 0 && (!words || !lhcbid || !u || !weight)) return false;
-  if (launch && (launch->block < 64 || launch->block > 1024 || launch->block % 64 || launch->grid < 0))
+  if (launch && (launch->block < 64 || launch->block > 1024 || launch->block % 64 || launch->grid < 0 ||
+                 launch->window_tile < 0 || launch->window_tile > 40 ||
+                 (launch->window_tile > 0 && launch->window_tile < 4)))
     return false;
   if ((int64_t)n_events * kLayers > INT32_MAX / 2) return false;
   return true;

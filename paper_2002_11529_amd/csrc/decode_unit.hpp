@@ -8,7 +8,7 @@ namespace utc {
 
 constexpr uint32_t kMaxBankWords = UTC_MAX_BANK_WORDS;
 constexpr int kMinCap = 256;         // smallest chunk of raw words staged in LDS per wavefront
-constexpr size_t kWaveLdsTarget = 10 * 1024;   // LDS per wavefront that keeps 16 waves per CU
+constexpr size_t kWaveLdsDefault = 10 * 1024;   // LDS per wavefront that keeps 16 waves per CU
 
 struct HitsOut {
   uint32_t* lhcbid;
@@ -45,10 +45,11 @@ __host__ __device__ inline size_t wave_scratch_bytes(int S, int cap) {
   return (b + 15) / 16 * 16;
 }
 
-// Largest chunk (a multiple of 64 words, at least kMinCap) whose scratch fits kWaveLdsTarget.
-inline int chunk_words(int S) {
+// Largest chunk (a multiple of 64 words, at least kMinCap) whose scratch fits `target` bytes of
+// LDS per wavefront.
+inline int chunk_words(int S, size_t target) {
   const size_t t = wave_table_bytes(S) + 16;
-  int cap = t < kWaveLdsTarget ? (int)((kWaveLdsTarget - t) / (5 * sizeof(uint16_t))) : 0;
+  int cap = t < target ? (int)((target - t) / (5 * sizeof(uint16_t))) : 0;
   cap = cap / 64 * 64;
   return cap < kMinCap ? kMinCap : (cap > (int)kMaxBankWords ? (int)kMaxBankWords : cap);
 }

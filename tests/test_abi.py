@@ -112,6 +112,11 @@ def test_host_checks_of_every_entry_point():
     lc = api.UtcLaunchConfig()
     lc.block, lc.grid = 256, -1
     assert decode(launch=lc) == -1
+    # window tile: 0 (default) or 4 .. 40 KiB per wavefront
+    for tile, ok in ((-1, False), (1, False), (3, False), (0, True), (4, True), (40, True), (41, False)):
+        lc = api.UtcLaunchConfig()
+        lc.block, lc.grid, lc.window_tile = 256, 0, tile
+        assert decode(launch=lc) == (-2 if ok else -1), tile
     # workspace one byte short
     assert decode(ws=one, ws_bytes=ws_dec - 1) == -2
 
@@ -132,6 +137,10 @@ def test_host_checks_of_every_entry_point():
         lc = api.UtcLaunchConfig()
         lc.block, lc.grid = block, 0
         assert (find(launch=lc, n_tracks=0) == 0) == ok, block
+    for tile, ok in ((-1, False), (2, False), (0, True), (4, True), (40, True), (41, False)):
+        lc = api.UtcLaunchConfig()
+        lc.block, lc.grid, lc.window_tile = 256, 0, tile
+        assert (find(launch=lc, n_tracks=0) == 0) == ok, tile
     for field, bad in (("max_hits", 0), ("max_hits", 33), ("n_sectors_search", 2), ("max_tracklets", -1)):
         q = api.compass_params(synth.make_compass_params())
         setattr(q, field, bad)

@@ -27,6 +27,9 @@ def test_launch_tag():
     assert bench.launch_tag({"block": 256, "grid": 512}, 1000) == "block=256 grid=512"
     assert bench.launch_tag({"block": 128, "grid": 2048}, 4000, 2) == "block=128 grid=per-item"
     assert bench.launch_tag({"block": 128, "grid": 1024}, 4000, 2) == "block=128 grid=1024"
+    # the LDS tile per wavefront, 0 standing for the default of 10 KiB
+    assert bench.launch_tag({"block": 512, "grid": 512, "tile": 16}, 1000) == "block=512 grid=512 tile=16"
+    assert bench.launch_tag({"block": 256, "grid": 0, "tile": 0}, 1000) == "block=256 grid=per-item tile=10"
 
 
 @pytest.fixture

@@ -57,7 +57,12 @@ def test_persistent_shapes_equal(uneven):
     n = int(h0["hit_offsets"][-1])
     for ld, lf in ((dict(block=128, grid=5), dict(block=64, grid=3)),
                    (dict(block=512, grid=256), dict(block=256, grid=1024)),
-                   (dict(block=64), dict(block=512)), (dict(block=256), dict(block=512, grid=7))):
+                   (dict(block=64), dict(block=512)), (dict(block=256), dict(block=512, grid=7)),
+                   # LDS tiles per wavefront: small chunks and window caches, large ones
+                   (dict(block=256, tile=4), dict(block=256, tile=4)),
+                   (dict(block=128, grid=7, tile=6), dict(block=512, grid=9, tile=8)),
+                   (dict(block=256, tile=16), dict(block=256, tile=24)),
+                   (dict(block=64, tile=40), dict(block=128, grid=5, tile=40))):
         h1, r1 = _batched(b, dv, geom, ld, lf)
         assert torch.equal(h0["hit_offsets"], h1["hit_offsets"])
         assert torch.equal(h0["u"][:n], h1["u"][:n]) and torch.equal(h0["lhcbid"][:n], h1["lhcbid"][:n])
@@ -116,3 +121,53 @@ def test_graph_replays_match_eager(uneven):
         for k in ("hit_idx", "qop", "chi2", "nhits"):
             assert torch.equal(res[k], r_ref[k]), (rep, k)
     assert int(flags.item()) == 0
+
+
+@pytest.mark.parametrize("tile", [0, 24])
+def test_graph_replays_persistent_counter(uneven, tile):
+    """A persistent Compass launch (its event counter is reset by a kernel inside the captured
+    graph) replayed several times, and a second graph with its own workspace replayed on another
+    stream, each against the eager result."""
+    b, dv, geom = uneven
+    lf = dict(block=256, grid=7, tile=tile)
+    h_ref, r_ref = _batched(b, dv, geom)
+    L = utc.library()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    graphs, outs = [], []
+    for st in streams:
+        hits = {k: torch.empty_like(v) for k, v in h_ref.items() if k != "error_flags"}
+        res = {k: torch.empty_like(v) for k, v in r_ref.items() if k != "error_flags"}
+        flags = torch.zeros(1, dtype=torch.int32, device=DEV)
+        wsd = torch.empty(L.ut_decode_workspace_bytes(b.n_events, b.detector.n_sectors),
+                          dtype=torch.uint8, device=DEV)
+        wsf = torch.empty(256, dtype=torch.uint8, device=DEV)
+        st.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(graph, stream=st):
+                utc.ut_decode(geom, dv["words"], dv["bank_offsets"], b.n_events, error_flags=flags,
+                              out=hits, workspace=wsd, launch=dict(block=128, grid=9, tile=tile))
+                utc.compass_find(geom, b.params, b.n_events, hits, *dv["vel"], dv["velo_offsets"],
+                                 error_flags=flags, out=res, workspace=wsf, launch=lf)
+        torch.cuda.current_stream().wait_stream(st)
+        graphs.append(graph)
+        outs.append((hits, res, flags))
+    n = int(h_ref["hit_offsets"][-1])
+    for rep in range(3):
+        for hits, res, _ in outs:
+            for k, v in list(hits.items()) + list(res.items()):
+                if k != "error_flags":   # the flag word is OR-ed into, never cleared, by the calls
+                    v.fill_(-7)
+        torch.cuda.synchronize()
+        _batched(b, dv, geom)          # eager work between the replays
+        for st, graph in zip(streams, graphs):
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                graph.replay()
+        torch.cuda.synchronize()
+        for hits, res, flags in outs:
+            assert torch.equal(hits["hit_offsets"], h_ref["hit_offsets"]), rep
+            assert torch.equal(hits["u"][:n], h_ref["u"][:n]), rep
+            for k in ("hit_idx", "qop", "chi2", "nhits"):
+                assert torch.equal(res[k], r_ref[k]), (rep, k)
+            assert int(flags.item()) == 0
