@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <stdint.h>
 
 #include "ut_compass.h"
@@ -24,6 +26,7 @@ struct Geom {
   float inv_sector_width;
   float y_begin, y_end;
   float weight_by_size[16];
+  float inv_a_up[4];   // 1 / a_kick rounded up (upper bounds for the pruning; unused if a <= 0)
   const float* u0;
 };
 
@@ -43,6 +46,8 @@ inline Geom make_geom(const utc_geometry& g) {
   d.y_begin = g.y_begin;
   d.y_end = g.y_end;
   for (int i = 0; i < 16; ++i) d.weight_by_size[i] = g.weight_by_size[i];
+  for (int l = 0; l < 4; ++l)
+    d.inv_a_up[l] = g.a_kick[l] > 0.0f ? nextafterf(1.0f / g.a_kick[l], INFINITY) : 0.0f;
   d.u0 = g.u0;
   return d;
 }
@@ -83,6 +88,20 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t x) {
 
 __device__ inline uint32_t wave_inclusive_max(uint32_t x) {
   return dpp_inclusive_scan(x, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_inclusive_max(x), 63);
+}
+
+// Unsigned keys in the order of the floats they stand for (-0 before +0; not for NaN).
+__device__ inline uint32_t float_order_key(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ inline float float_from_order_key(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
 }
 
 __device__ inline uint32_t wave_sum(uint32_t x) {

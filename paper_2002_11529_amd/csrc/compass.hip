@@ -10,6 +10,10 @@
 
 namespace utc {
 
+// LDS words of the event's bank offsets (nb + 1) and the six control words after them, rounded to
+// 16 bytes.
+__host__ __device__ inline int hoff_words(int nb) { return (nb + 1 + 6 + 3) & ~3; }
+
 // kGreedy: the paper's search variant (max_tracklets > 0), a kernel of its own so that its code
 // does not weigh on the register allocation of the default search
 // The next group of tracks for the calling wave: groups are handed out in order from a counter in
@@ -34,9 +38,12 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
   const int tid = threadIdx.x, bs = blockDim.x;
   const int wid = tid / kWave, nwaves = bs / kWave;
   uint32_t* s_hoff = reinterpret_cast<uint32_t*>(smem);
-  float* s_u = reinterpret_cast<float*>(s_hoff + ((nb + 1 + 3) & ~3));
-  uint32_t* s_next = s_hoff + nb + 1;   // group counter, in the padding after the offsets
+  float* s_u = reinterpret_cast<float*>(s_hoff + hoff_words(nb));
+  uint32_t* s_next = s_hoff + nb + 1;   // group counter, after the offsets
   uint32_t* s_event = s_hoff + nb + 2;  // the workgroup's next event (persistent grids)
+  uint32_t* s_ycov = s_hoff + nb + 3;   // [3] y range every strip of the event covers (ordered
+                                        // keys of the largest y_begin and the smallest y_end), and
+                                        // whether some strip's range is not a number
   char* gbase = reinterpret_cast<char*>(s_u + u_cap);
   const GroupScratch gs = carve_group(gbase + (size_t)wid * group_scratch_bytes(p.max_hits, kGreedy),
                                       p.max_hits, kGreedy);
@@ -60,7 +67,12 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
         if (j <= nb) s_hoff[j] = v[q] - H;
       }
     }
-    if (tid == 0) *s_next = (uint32_t)nwaves;   // groups 0 .. nwaves-1 go to the waves in order
+    if (tid == 0) {
+      *s_next = (uint32_t)nwaves;   // groups 0 .. nwaves-1 go to the waves in order
+      s_ycov[0] = 0u;
+      s_ycov[1] = ~0u;
+      s_ycov[2] = 0u;
+    }
     __syncthreads();
     const uint32_t nh = s_hoff[nb];
     bool overflow = false;
@@ -91,6 +103,37 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
         }
       }
     }
+    // the y range that every strip of the event covers: a track whose y lies inside it at a layer
+    // passes the per-hit y test of every hit there, so the window tile then skips the per-hit
+    // y_begin / y_end loads (one coalesced pass over the event's ranges instead of gathers per
+    // window slot; with a range that is not a number the per-hit test is kept for every track)
+    if (hyb) {
+      uint32_t kb = 0u, ke = ~0u;
+      bool bad = false;
+      for (uint32_t k0 = 0; k0 < nh; k0 += 4 * bs) {
+        float vb[4], ve[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t k = k0 + q * bs + tid;
+          vb[q] = k < nh ? hyb[(int64_t)H + k] : -INFINITY;
+          ve[q] = k < nh ? hye[(int64_t)H + k] : INFINITY;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bad |= !(vb[q] == vb[q]) || !(ve[q] == ve[q]);
+          kb = max(kb, float_order_key(vb[q]));
+          ke = min(ke, float_order_key(ve[q]));
+        }
+      }
+      kb = wave_max_u32(kb);
+      ke = ~wave_max_u32(~ke);
+      const bool any_bad = wave_any(bad);
+      if (lane_id() == 0) {
+        atomicMax(&s_ycov[0], kb);
+        atomicMin(&s_ycov[1], ke);
+        if (any_bad) atomicOr(&s_ycov[2], 1u);
+      }
+    }
     if (overflow && tid == 0) raise_flag(flags, UTC_FLAG_LAYER_OVERFLOW);
     __syncthreads();
     EventView ev;
@@ -103,6 +146,9 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     ev.hoff = s_hoff;
     ev.first = H;
     ev.overflow = overflow;
+    // an empty or all-NaN-free range gives y_lo > y_hi, which no track lies inside
+    ev.y_lo = (hyb && s_ycov[2] == 0u) ? float_from_order_key(s_ycov[0]) : INFINITY;
+    ev.y_hi = (hyb && s_ycov[2] == 0u) ? float_from_order_key(s_ycov[1]) : -INFINITY;
     ev.stride = staged ? 1u : (ncoarse > 0 ? stride : 0u);
     const uint32_t t0 = velo_offsets[e], t1 = velo_offsets[e + 1];
     const uint32_t ngroups = (t1 - t0 + kGroupTracks - 1) / kGroupTracks;
@@ -153,7 +199,7 @@ __global__ void k_compass_start(uint32_t* ev_counter, uint32_t grid) {
 }
 
 size_t compass_lds_bytes(int S, int max_hits, int waves, int u_cap, bool greedy) {
-  const size_t hoff = 4 * (size_t)(((kLayers * S + 1) + 3) & ~3);
+  const size_t hoff = 4 * (size_t)hoff_words(kLayers * S);
   return hoff + 4 * (size_t)u_cap + (size_t)waves * group_scratch_bytes(max_hits, greedy);
 }
 

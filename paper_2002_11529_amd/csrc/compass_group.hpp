@@ -43,6 +43,7 @@ struct EventView {
   const uint32_t* hoff;        // [4S+1] event-local first hit of each bank
   int64_t first;               // global index of the event's first hit
   bool overflow;               // an (event, layer) holds more than 32767 hits
+  float y_lo, y_hi;            // every strip of the event covers [y_lo, y_hi] (empty if unknown)
   uint32_t stride;             // u_lds[k] = u of hit k*stride (1: every hit; 0: nothing staged)
 };
 
@@ -292,13 +293,15 @@ __device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int
   return f;
 }
 
-// Upper bound of |q| * sqrt(Saa) over the 4-hit candidates of a pair, in binary32 rounded up.
+// Upper bound of |q| * sqrt(Saa) over the 4-hit candidates of a pair, in binary32 rounded up (the
+// reciprocals of the kick factors are rounded up on the host; the final factor 1.001 covers the
+// roundings of the products and of the hardware square root, which is within 1 ulp).
 __device__ inline float pair_z(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
                                int B, int C1, int C2, int jA, int jB, float mA, float slope,
                                const AnchorFit& f) {
   const float rA = s.tm[tile_at(t, A, jA)] - s.xs[t * 4 + A];
   const float rB = s.tm[tile_at(t, B, jB)] - s.xs[t * 4 + B];
-  float rmax = fmaxf(fabsf(rA) / g.a_kick[A], fabsf(rB) / g.a_kick[B]);
+  float rmax = fmaxf(fabsf(rA) * g.inv_a_up[A], fabsf(rB) * g.inv_a_up[B]);
   float k = (float)f.S;
   const int Cs[2] = {C1, C2};
 #pragma unroll
@@ -307,22 +310,52 @@ __device__ inline float pair_z(const Geom& g, const CPar& p, const GroupScratch&
     completion_bounds(g, p, s, t, A, Cs[i], mA, slope, lo, hi);
     const float xsl = s.xs[t * 4 + Cs[i]];
     const float a = g.a_kick[Cs[i]];
-    rmax = fmaxf(rmax, fmaxf(fabsf(lo - xsl), fabsf(hi - xsl)) / a);
+    rmax = fmaxf(rmax, fmaxf(fabsf(lo - xsl), fabsf(hi - xsl)) * g.inv_a_up[Cs[i]]);
     k += s.wmax[t * 4 + Cs[i]] * a * a;
   }
-  return rmax * sqrtf(k) * 1.001f;
+  return rmax * __builtin_amdgcn_sqrtf(k) * 1.001f;
 }
 
-// Completion hits of layer Cl (mask m) that can still be in a selected candidate, given U.
-__device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
-                                      const AnchorFit& f, float Z, float U) {
+// The part of the test that is common to every completion hit of a pair: T, the pair-level test,
+// and the right-hand side of the hit test divided through by (S + k).  In exact arithmetic the hit
+// test  C (S + k) + S w e^2 <= T S^2 (S + k)  is  S w e^2 <= (S + k) D,  D = T S^2 - C; D is taken
+// with an added 2^-50 (T S^2 + C), more than its rounding errors, and the right-hand side with a
+// factor 1 + 1e-12, so that the binary64 evaluation keeps every hit the exact test keeps.
+struct PruneBound {
+  double S, N;     // the pair's k_A + k_B and sum w a r
+  double D;        // slackened T S^2 - C, times 1 + 1e-12
+  int state;       // 0: test each hit; 1: keep every hit (premises fail); 2: no hit can be kept
+};
+
+__device__ inline PruneBound prune_bound(const AnchorFit& f, float Z, float U) {
   constexpr float u = 5.9604644775390625e-08f;   // 2^-24
-  const float E = (7.0f * u * (2.0f * U + 1.0f) + 2.02f * u * sqrtf(2.0f * U + 1.0f) * Z) * 1.001f;
-  if (!(E <= U + 1.0f) || !isfinite(f.C)) return m;   // premises fail: keep all
+  // the hardware square root is within 1 ulp; the factor 1.001 covers it
+  const float E = (7.0f * u * (2.0f * U + 1.0f) + 2.02f * u * __builtin_amdgcn_sqrtf(2.0f * U + 1.0f) * Z) *
+                  1.001f;
+  PruneBound b;
+  b.S = f.S;
+  b.N = f.N;
+  b.D = 0.0;
+  b.state = 1;
+  if (!(E <= U + 1.0f) || !isfinite(f.C)) return b;   // premises fail: keep all
   const double T = (double)U + 4.0 * (double)E + 1e-6 * ((double)U + 1.0);
-  const double S2 = f.S * f.S;
-  if (f.C > T * S2) return 0u;   // chi2_AB alone exceeds the bound
+  const double TS2 = T * (f.S * f.S);
+  if (f.C > TS2) {   // chi2_AB alone exceeds the bound
+    b.state = 2;
+    return b;
+  }
+  b.D = ((TS2 - f.C) + 0x1p-50 * (TS2 + f.C)) * (1.0 + 1e-12);
+  b.state = 0;
+  return b;
+}
+
+// Completion hits of layer Cl (mask m) that can still be in a selected candidate.
+__device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int t, int Cl, uint32_t m,
+                                      const PruneBound& b) {
+  if (b.state == 1) return m;
+  if (b.state == 2) return 0u;
   const double a = g.a_kick[Cl];
+  const double a2 = a * a, aN = a * b.N;
   const float xsl = s.xs[t * 4 + Cl];
   uint32_t keep = 0;
   for (uint32_t mm = m; mm; mm &= mm - 1) {
@@ -330,10 +363,8 @@ __device__ inline uint32_t prune_mask(const Geom& g, const GroupScratch& s, int 
     const int o = tile_at(t, Cl, (int)j);
     const double r = (double)(s.tm[o] - xsl);
     const double w = s.tw[o];
-    const double k = w * a * a;
-    const double e = r * f.S - a * f.N;
-    const double lhs = f.C * (f.S + k) + f.S * w * e * e;
-    if (lhs <= T * S2 * (f.S + k) * (1.0 + 1e-12)) keep |= 1u << j;
+    const double e = r * b.S - aN;
+    if ((b.S * w) * (e * e) <= (b.S + w * a2) * b.D) keep |= 1u << j;
   }
   return keep;
 }
@@ -455,8 +486,9 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
         const float slope = (s.tm[tile_at(tt, B, jB)] - mA) * inv_dz_ab;
         const float Z = pair_z(g, p, s, tt, A, B, C1, C2, jA, jB, mA, slope, af);
         if (isfinite(Z)) {
-          m1 = prune_mask(g, s, tt, C1, m1, af, Z, U);
-          m2 = m1 ? prune_mask(g, s, tt, C2, m2, af, Z, U) : 0u;
+          const PruneBound pb = prune_bound(af, Z, U);
+          m1 = prune_mask(g, s, tt, C1, m1, pb);
+          m2 = m1 ? prune_mask(g, s, tt, C2, m2, pb) : 0u;
         }
       }
     }
@@ -725,8 +757,11 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
     s.tx[t] = tx;
     s.best[t] = kNoKey;
   }
-  // tile: x at the track's y and weight of each window hit; -1 marks a strip that does not cover y
-  const float g_yb = g.y_begin, g_ye = g.y_end;
+  // tile: x at the track's y and weight of each window hit; -1 marks a strip that does not cover y.
+  // Per-hit strip ranges are read only when the track's y is outside the range that every strip
+  // of the event covers; without them (NULL) every strip spans the detector's range.
+  const bool per_hit_y = ev.yb_glb && !(ev.y_lo <= yl && yl <= ev.y_hi);
+  const float g_yb = ev.yb_glb ? -INFINITY : g.y_begin, g_ye = ev.yb_glb ? INFINITY : g.y_end;
   uint32_t umask = 0;
   float wm = 0.0f;
   for (int j0 = 0; j0 < wn; j0 += 8) {
@@ -742,7 +777,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
       if (in) {
         uu[q] = ev_u<kULds>(ev, k);
         ww[q] = ev_w<kWLds>(ev, k);
-        if (ev.yb_glb) {
+        if (per_hit_y) {
           yb[q] = ev.yb_glb[ev.first + k];
           ye[q] = ev.ye_glb[ev.first + k];
         }

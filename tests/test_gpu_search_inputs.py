@@ -109,3 +109,23 @@ def test_binding_rejects_wrong_tensors(base):
     assert not strided.is_contiguous()
     with pytest.raises(ValueError):
         utc.ut_decode(geom, strided, dv["bank_offsets"], b.n_events)
+
+
+def test_strip_ranges_with_nan_and_narrow_strips(base):
+    """A strip range that is not a number makes its hit unusable; a few narrow strips in some
+    events shrink the range that every strip of the event covers, so those events' tracks take the
+    per-hit test while the other events' tracks skip it."""
+    b, d = base
+    rng = np.random.default_rng(9)
+    n = int(d["hit_offsets"][-1])
+    d2 = dict(d)
+    yb = d["y_begin"][:n].copy()
+    ye = d["y_end"][:n].copy()
+    pick = rng.choice(n, 40, replace=False)
+    yb[pick[:10]] = np.nan
+    ye[pick[10:20]] = np.nan
+    yb[pick[20:30]] = rng.uniform(-5.0, 5.0, 10).astype(np.float32)      # narrow strips
+    ye[pick[30:40]] = rng.uniform(-5.0, 5.0, 10).astype(np.float32)
+    d2["y_begin"], d2["y_end"] = yb, ye
+    r, c = _search_both(b, b.detector, d2)
+    assert (c["nhits"] > 0).sum() > 0
