@@ -18,6 +18,7 @@ namespace utc {
 
 constexpr int kGroupTracks = 16;
 constexpr int kPruneMinCandidates = 256;   // 4-hit candidates of a batch below which no pruning
+constexpr uint32_t kFilterMinPairs = 128;   // anchor pairs of a group below which no seeds
 
 struct CPar {
   float W;            // window half-width (mm)
@@ -72,11 +73,15 @@ struct GroupScratch {
   uint32_t* umask;    // [64] usable window slots (strip covers the track's y)
   float* wmax;        // [64] largest weight of the usable slots
   uint32_t* poff;     // [17] pair offsets of the tracks
-  uint32_t* bp;       // [64] batch of anchor pairs that passed the slope test: t | jA<<8 | jB<<16
+  uint32_t* bp;       // [128] anchor pairs that passed the slope test: t | jA<<8 | jB<<16 (a batch
+                      // of at most 64 at the front; in the pruned 4-hit search the pairs kept so
+                      // far followed by the next pairs to test)
   uint32_t* bm1;      // [64] their completion masks in layer C1
   uint32_t* bm2;      // [64] their completion masks in layer C2
   uint32_t* boff;     // [65] candidate offsets of the batch
   uint32_t* mk;       // [64] pair starting at each candidate slot of a chunk (index + 1, 0 = none)
+  uint32_t* irem;     // [16 * max_hits] passing anchor-B slots of each work item (pruned search)
+  float* tz;          // [16] bound of |q| sqrt(Saa) over every candidate of each track
   // the paper's search only: window slots in the order the search walks them (central sector
   // first, see build_walk_order), walk[p] = slot at walk position p, iwalk[slot] = its position
   uint8_t* walk;      // [max_hits][64]
@@ -85,7 +90,8 @@ struct GroupScratch {
 
 __host__ __device__ inline size_t group_scratch_bytes(int max_hits, bool greedy) {
   const size_t b = 16 * kGroupTracks + 8 * 64 + 2 * sizeof(float) * 64 * (size_t)max_hits + 4 * 64 +
-                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 3 * 4 * 64 + 4 * 65 + 4 * 64 +
+                   4 * kGroupTracks + 4 * 64 + 4 * (kGroupTracks + 1) + 4 * 128 + 2 * 4 * 64 + 4 * 65 +
+                   4 * 64 + 4 * kGroupTracks * (size_t)max_hits + 4 * kGroupTracks +
                    (greedy ? 2 * 64 * (size_t)max_hits : 0);
   return (b + 15) / 16 * 16;
 }
@@ -103,11 +109,13 @@ __device__ inline GroupScratch carve_group(char* p, int max_hits, bool greedy) {
   s.nwin = reinterpret_cast<int32_t*>(s.tx + kGroupTracks);
   s.poff = reinterpret_cast<uint32_t*>(s.nwin + 64);
   s.bp = s.poff + kGroupTracks + 1;
-  s.bm1 = s.bp + 64;
+  s.bm1 = s.bp + 128;
   s.bm2 = s.bm1 + 64;
   s.boff = s.bm2 + 64;
   s.mk = s.boff + 65;
-  s.walk = greedy ? reinterpret_cast<uint8_t*>(s.mk + 64) : nullptr;
+  s.irem = s.mk + 64;
+  s.tz = reinterpret_cast<float*>(s.irem + kGroupTracks * max_hits);
+  s.walk = greedy ? reinterpret_cast<uint8_t*>(s.tz + kGroupTracks) : nullptr;
   s.iwalk = greedy ? s.walk + 64 * max_hits : nullptr;
   return s;
 }
@@ -293,34 +301,16 @@ __device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int
   return f;
 }
 
-// Upper bound of |q| * sqrt(Saa) over the 4-hit candidates of a pair, in binary32 rounded up (the
-// reciprocals of the kick factors are rounded up on the host; the final factor 1.001 covers the
-// roundings of the products and of the hardware square root, which is within 1 ulp).
-__device__ inline float pair_z(const Geom& g, const CPar& p, const GroupScratch& s, int t, int A,
-                               int B, int C1, int C2, int jA, int jB, float mA, float slope,
-                               const AnchorFit& f) {
-  const float rA = s.tm[tile_at(t, A, jA)] - s.xs[t * 4 + A];
-  const float rB = s.tm[tile_at(t, B, jB)] - s.xs[t * 4 + B];
-  float rmax = fmaxf(fabsf(rA) * g.inv_a_up[A], fabsf(rB) * g.inv_a_up[B]);
-  float k = (float)f.S;
-  const int Cs[2] = {C1, C2};
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    float lo, hi;
-    completion_bounds(g, p, s, t, A, Cs[i], mA, slope, lo, hi);
-    const float xsl = s.xs[t * 4 + Cs[i]];
-    const float a = g.a_kick[Cs[i]];
-    rmax = fmaxf(rmax, fmaxf(fabsf(lo - xsl), fabsf(hi - xsl)) * g.inv_a_up[Cs[i]]);
-    k += s.wmax[t * 4 + Cs[i]] * a * a;
-  }
-  return rmax * __builtin_amdgcn_sqrtf(k) * 1.001f;
-}
-
 // The part of the test that is common to every completion hit of a pair: T, the pair-level test,
 // and the right-hand side of the hit test divided through by (S + k).  In exact arithmetic the hit
 // test  C (S + k) + S w e^2 <= T S^2 (S + k)  is  S w e^2 <= (S + k) D,  D = T S^2 - C; D is taken
 // with an added 2^-50 (T S^2 + C), more than its rounding errors, and the right-hand side with a
 // factor 1 + 1e-12, so that the binary64 evaluation keeps every hit the exact test keeps.
+// Z, the bound of |q| sqrt(Saa) that the margin E takes, is per track: every hit of a candidate is
+// a usable window slot, so |q| <= max |r / a| over the track's usable window slots of the four
+// layers (q is a weighted mean of the r / a of its hits), and Saa <= sum over layers of the largest
+// usable weight times a^2.  Computed in binary32 from reciprocals of the kick factors rounded up on
+// the host and the hardware square root (within 1 ulp); the factor 1.001 covers those roundings.
 struct PruneBound {
   double S, N;     // the pair's k_A + k_B and sum w a r
   double D;        // slackened T S^2 - C, times 1 + 1e-12
@@ -455,41 +445,16 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
     full_tot = wave_sum(full);
   }
   if (nhits == 4 && p.prune && full_tot > (uint32_t)kPruneMinCandidates) {
-    // one seed per track and batch: the pair with the lowest two-anchor chi2, with the completion
-    // hits nearest to its fit; the seed's chi2 bounds the rest of the track's candidates
-    const bool multi = (uint32_t)lane < np && m1 && m2 && __popc(m1) * __popc(m2) > 1;
-    AnchorFit af;
-    if (lane < kGroupTracks) s.lbk[lane] = kNoKey;
-    wave_sync();
-    if (multi) {
-      af = anchor_fit(g, s, tt, A, B, jA, jB);
-      const float c2ab = __fdividef((float)af.C, (float)(af.S * af.S));
-      atomicMin(&s.lbk[tt], ((unsigned long long)__float_as_uint(fabsf(c2ab)) << 32) | (unsigned)lane);
-    }
-    wave_sync();
-    if (multi && (uint32_t)(s.lbk[tt] & 0xFFFFFFFFull) == (uint32_t)lane) {
-      uint32_t code[4];
-      code[A] = (uint32_t)jA + 1u;
-      code[B] = (uint32_t)jB + 1u;
-      code[C1] = nearest_slot(g, s, tt, C1, m1, af.qab) + 1u;
-      code[C2] = nearest_slot(g, s, tt, C2, m2, af.qab) + 1u;
-      float qs, cs;
-      fit_codes(g, s, tt, code, qs, cs);
-      atomicMin(&s.best[tt], make_key(4, cs, code));
-    }
-    wave_sync();
-    if (multi) {
+    // the completion hits that can still be in the track's selected candidate, against the best
+    // 4-hit chi2 found so far (the track's seed at least, see seed_tracks)
+    if ((uint32_t)lane < np && m1 && m2 && __popc(m1) * __popc(m2) > 1) {
       const unsigned long long bk = s.best[tt];
       const float U = __uint_as_float((uint32_t)(bk >> 24));
-      if (bk != kNoKey && isfinite(U)) {
-        const float mA = s.tm[tile_at(tt, A, jA)];
-        const float slope = (s.tm[tile_at(tt, B, jB)] - mA) * inv_dz_ab;
-        const float Z = pair_z(g, p, s, tt, A, B, C1, C2, jA, jB, mA, slope, af);
-        if (isfinite(Z)) {
-          const PruneBound pb = prune_bound(af, Z, U);
-          m1 = prune_mask(g, s, tt, C1, m1, pb);
-          m2 = m1 ? prune_mask(g, s, tt, C2, m2, pb) : 0u;
-        }
+      const float Z = s.tz[tt];
+      if (bk != kNoKey && isfinite(U) && isfinite(Z)) {
+        const PruneBound pb = prune_bound(anchor_fit(g, s, tt, A, B, jA, jB), Z, U);
+        m1 = prune_mask(g, s, tt, C1, m1, pb);
+        m2 = m1 ? prune_mask(g, s, tt, C2, m2, pb) : 0u;
       }
     }
   }
@@ -552,6 +517,69 @@ __device__ inline void run_batch(const Geom& g, const CPar& p, const GroupScratc
   wave_sync();
 }
 
+// Seeds of the pruned 4-hit search.  Each work item (track, usable anchor-A slot) with its passing
+// anchor-B slots `rem` proposes the pair with the lowest two-anchor chi2 (approximate arithmetic:
+// the choice only steers the pruning); per track the lowest proposal is kept in s.lbk.
+__device__ inline void propose_seed(const Geom& g, const GroupScratch& s, int tt, int A, int B,
+                                    uint32_t jA, uint32_t rem) {
+  const int oA = tile_at(tt, A, (int)jA);
+  const float aA = g.a_kick[A], aB = g.a_kick[B];
+  const float wA = s.tw[oA];
+  const float rAaB = (s.tm[oA] - s.xs[tt * 4 + A]) * aB;
+  const float kA = wA * aA * aA;
+  const float xsB = s.xs[tt * 4 + B];
+  unsigned long long k = kNoKey;
+  for (uint32_t mm = rem; mm; mm &= mm - 1u) {
+    const uint32_t jB = (uint32_t)__builtin_ctz(mm);
+    const int oB = tile_at(tt, B, (int)jB);
+    const float wB = s.tw[oB];
+    const float d = rAaB - (s.tm[oB] - xsB) * aA;
+    const float c2 = __fdividef(wA * wB * d * d, kA + wB * aB * aB);
+    k = min(k, ((unsigned long long)__float_as_uint(fabsf(c2)) << 32) | (jA << 8) | jB);
+  }
+  if (k != kNoKey) atomicMin(&s.lbk[tt], k);
+}
+
+// Each track's proposed seed pair (lanes 0..15, track = lane) is completed with the compatible hits
+// nearest to its two-anchor fit; when both completion layers have one this is a 4-hit candidate of
+// the track, and its key goes into the track's minimum, so that its chi2 bounds the rest.
+__device__ inline void seed_tracks(const Geom& g, const CPar& p, const GroupScratch& s, int A, int B,
+                                   int C1, int C2, float inv_dz_ab, bool want_track) {
+  const int t = lane_id();
+  if (t >= kGroupTracks || !want_track) return;
+  const unsigned long long key = s.lbk[t];
+  if (key == kNoKey) return;
+  const int jA = (int)((key >> 8) & 0xFFu), jB = (int)(key & 0xFFu);
+  const float mA = s.tm[tile_at(t, A, jA)];
+  const float slope = (s.tm[tile_at(t, B, jB)] - mA) * inv_dz_ab;
+  uint32_t m1, m2;
+  completion_ranges(g, p, s, t, A, C1, C2, mA, slope, m1, m2);
+  m1 &= s.umask[t * 4 + C1];
+  m2 &= s.umask[t * 4 + C2];
+  if (!m1 || !m2) return;
+  const AnchorFit af = anchor_fit(g, s, t, A, B, jA, jB);
+  uint32_t code[4];
+  code[A] = (uint32_t)jA + 1u;
+  code[B] = (uint32_t)jB + 1u;
+  code[C1] = nearest_slot(g, s, t, C1, m1, af.qab) + 1u;
+  code[C2] = nearest_slot(g, s, t, C2, m2, af.qab) + 1u;
+  float qs, cs;
+  fit_codes(g, s, t, code, qs, cs);
+  s.best[t] = min(s.best[t], make_key(4, cs, code));
+}
+
+// Whether anchor pair (jA, jB) of track tt can hold the track's selected 4-hit candidate: not when
+// its two-anchor chi2 alone exceeds the bound T of the best 4-hit chi2 found so far (see
+// prune_bound).
+__device__ inline bool pair_can_win(const Geom& g, const GroupScratch& s, int tt, int A, int B, int jA,
+                                    int jB) {
+  const unsigned long long bk = s.best[tt];
+  const float U = __uint_as_float((uint32_t)(bk >> 24));
+  const float Z = s.tz[tt];
+  if (bk == kNoKey || !isfinite(U) || !isfinite(Z)) return true;
+  return prune_bound(anchor_fit(g, s, tt, A, B, jA, jB), Z, U).state != 2;
+}
+
 // The candidates of one direction with `nhits` hits (4: both completion layers; 3: one of them) for
 // the tracks with want_lane set (read on their layer-0 lane).  Work items are (track, anchor-A
 // hit); each finds its passing anchor-B hits as one slot range, and the passing pairs are handed
@@ -564,17 +592,22 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
   dir_layers(dir, A, B, C1, C2);
   const float inv_dz_ab = 1.0f / (g.z_layer[B] - g.z_layer[A]);
   if (nhits == 0 && lane < kGroupTracks) s.lbk[lane] = 0ull;   // tracklets found per track
+  // 4-hit search with pruning allowed: the passing anchor-B slots of every work item first; when
+  // the group has more than kFilterMinPairs anchor pairs, a seed candidate per track, and then only
+  // the pairs whose two-anchor chi2 leaves room under the best chi2 found so far are batched (kept
+  // pairs accumulate in s.bp until a batch of 64 is full)
+  const bool slots_first = nhits == 4 && p.prune;
+  bool pruned = false;
+  if (slots_first && lane < kGroupTracks) s.lbk[lane] = kNoKey;     // seed proposal per track
   const uint32_t cnt = (l == 0 && want_lane) ? (uint32_t)s.nwin[t * 4 + A] : 0u;
   uint32_t total;
   const uint32_t off = wave_excl_scan(cnt, &total);
   if (l == 0) s.poff[t] = off;
   if (lane == 0) s.poff[kGroupTracks] = total;
   wave_sync();
-  for (uint32_t base = 0; base < total; base += kWave) {
-    const uint32_t it = base + (uint32_t)lane;
-    uint32_t rem = 0;    // anchor-B slots still to be paired with this lane's anchor-A hit
-    uint32_t head = 0;   // track | anchor-A slot << 8
-    // track of each item: markers at the tracks' first items, then a running maximum
+  // track of each work item of the chunk at `base`: markers at the tracks' first items, then a
+  // running maximum (every lane calls it)
+  auto item_track = [&](uint32_t base) -> int {
     s.mk[lane] = 0u;
     wave_sync();
     if (l == 0 && cnt > 0u && off >= base && off < base + (uint32_t)kWave) s.mk[off - base] = (uint32_t)t + 1u;
@@ -582,13 +615,50 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
     wave_sync();
     uint32_t mtr = s.mk[lane];
     if (lane == 0 && before) mtr = max(mtr, (uint32_t)((63 - __builtin_clzll(before)) >> 2) + 1u);
-    const uint32_t tr1 = wave_inclusive_max(mtr);
+    return (int)wave_inclusive_max(mtr) - 1;
+  };
+  if (slots_first) {
+    uint32_t npairs = 0;
+    for (uint32_t base = 0; base < total; base += kWave) {
+      const uint32_t it = base + (uint32_t)lane;
+      const int tt = item_track(base);
+      uint32_t rem = 0;
+      if (it < total) {
+        const uint32_t jA = it - s.poff[tt];
+        if ((s.umask[tt * 4 + A] >> jA) & 1u) {
+          const float mA = s.tm[tile_at(tt, A, (int)jA)];
+          rem = slope_range(s, tt, B, mA, inv_dz_ab, s.tx[tt], p.slope_tol) & s.umask[tt * 4 + B];
+        }
+        s.irem[it] = rem;
+      }
+      npairs += wave_sum((uint32_t)__popc(rem));
+    }
+    pruned = npairs > kFilterMinPairs;
+    wave_sync();
+    if (pruned) {
+      for (uint32_t base = 0; base < total; base += kWave) {
+        const uint32_t it = base + (uint32_t)lane;
+        const int tt = item_track(base);
+        if (it < total) propose_seed(g, s, tt, A, B, it - s.poff[tt], s.irem[it]);
+      }
+      wave_sync();
+      seed_tracks(g, p, s, A, B, C1, C2, inv_dz_ab, __shfl((int)want_lane, (lane & 15) * 4, kWave) != 0);
+      wave_sync();
+    }
+  }
+  uint32_t nkeep = 0;   // pruned search: pairs kept in s.bp[0, nkeep), waiting for a full batch
+  for (uint32_t base = 0; base < total; base += kWave) {
+    const uint32_t it = base + (uint32_t)lane;
+    uint32_t rem = 0;    // anchor-B slots still to be paired with this lane's anchor-A hit
+    uint32_t head = 0;   // track | anchor-A slot << 8
+    const int tt = item_track(base);
     if (it < total) {
-      const int tt = (int)tr1 - 1;
       // the paper's search takes the anchor-A hits in walk order, the exhaustive one in slot order
       const uint32_t jA = nhits == 0 ? walk_slot(s, tt, A, it - s.poff[tt]) : it - s.poff[tt];
       head = (uint32_t)tt | (jA << 8);
-      if ((s.umask[tt * 4 + A] >> jA) & 1u) {
+      if (slots_first) {
+        rem = s.irem[it];
+      } else if ((s.umask[tt * 4 + A] >> jA) & 1u) {
         const float mA = s.tm[tile_at(tt, A, (int)jA)];
         rem = slope_range(s, tt, B, mA, inv_dz_ab, s.tx[tt], p.slope_tol) & s.umask[tt * 4 + B];
         if (nhits == 0) rem = to_walk_mask(s, tt, B, rem);   // anchor-B hits in walk order too
@@ -606,12 +676,39 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
         uint32_t jB = (uint32_t)__builtin_ctz(rem);
         if (nhits == 0) jB = walk_slot(s, (int)(head & 0xFFu), B, jB);
         rem &= rem - 1u;
-        s.bp[o + k] = head | (jB << 16);
+        s.bp[nkeep + o + k] = head | (jB << 16);
       }
       wave_sync();
-      run_batch(g, p, s, A, B, C1, C2, inv_dz_ab, nhits, min(tot, (uint32_t)kWave));
+      const uint32_t np = min(tot, (uint32_t)kWave);
+      if (!pruned) {
+        run_batch(g, p, s, A, B, C1, C2, inv_dz_ab, nhits, np);
+        continue;
+      }
+      // the new pairs s.bp[nkeep, nkeep + np): the ones that can hold their track's winner are
+      // moved down behind the kept ones
+      uint32_t pr = 0u;
+      bool kp = false;
+      if ((uint32_t)lane < np) {
+        pr = s.bp[nkeep + (uint32_t)lane];
+        kp = pair_can_win(g, s, (int)(pr & 0xFFu), A, B, (int)((pr >> 8) & 0xFFu), (int)(pr >> 16));
+      }
+      const uint64_t km = ballot(kp);
+      wave_sync();
+      if (kp) s.bp[nkeep + lanes_before(km)] = pr;
+      nkeep += (uint32_t)__popcll(km);
+      wave_sync();
+      if (nkeep >= (uint32_t)kWave) {
+        run_batch(g, p, s, A, B, C1, C2, inv_dz_ab, nhits, (uint32_t)kWave);
+        const uint32_t rest = nkeep - (uint32_t)kWave;
+        const uint32_t v = (uint32_t)lane < rest ? s.bp[kWave + lane] : 0u;
+        wave_sync();
+        if ((uint32_t)lane < rest) s.bp[lane] = v;
+        nkeep = rest;
+        wave_sync();
+      }
     }
   }
+  if (nkeep > 0u) run_batch(g, p, s, A, B, C1, C2, inv_dz_ab, nhits, nkeep);
   wave_sync();
 }
 
@@ -796,6 +893,18 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
       }
     }
   }
+  // per-track bound Z of |q| sqrt(Saa) for the pruning margin: the largest |r| / a over the
+  // usable window slots and the sum of the largest usable weight times a^2, over the four layers
+  float rz = 0.0f;
+  for (uint32_t mm = umask; mm; mm &= mm - 1u)
+    rz = fmaxf(rz, fabsf(s.tm[tile_at(t, l, (int)__builtin_ctz(mm))] - xs));
+  rz *= g.inv_a_up[l];
+  float kz = wm * g.a_kick[l] * g.a_kick[l];
+  rz = fmaxf(rz, __shfl_xor(rz, 1, kWave));
+  rz = fmaxf(rz, __shfl_xor(rz, 2, kWave));
+  kz = kz + __shfl_xor(kz, 1, kWave);
+  kz = kz + __shfl_xor(kz, 2, kWave);
+  if (l == 0) s.tz[t] = p.prune ? rz * __builtin_amdgcn_sqrtf(kz) * 1.001f : INFINITY;
   s.umask[lane] = umask;
   s.wmax[lane] = wm;
   if constexpr (kGreedy) {
