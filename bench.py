@@ -684,6 +684,16 @@ def bench_fitgrad(args, dev):
 
     ms_fb = timed(lambda i: call(copies[i % R], True), args.steps)
     ms_f = timed(lambda i: call(copies[i % R], False), args.steps)
+    # the same fits on the hits frozen once in track-major form (40 B per track, no gathers)
+    for c in copies:
+        c["fz"] = utc.compass_fit_freeze(geom, c["idx"], c["u"], c["w"], c["id"])
+    ms_freeze = timed(lambda i: utc.compass_fit_freeze(geom, copies[i % R]["idx"], copies[i % R]["u"],
+                                                       copies[i % R]["w"], copies[i % R]["id"],
+                                                       out=copies[i % R]["fz"]), args.steps)
+    ms_fz = timed(lambda i: utc.compass_fit_grad_frozen(geom, copies[i % R]["fz"], *copies[i % R]["st"],
+                                                        copies[i % R]["qop"], copies[i % R]["off"],
+                                                        out=copies[i % R]["out"], workspace=ws),
+                  args.steps)
     out = copies[0]["out"]
     # the same work, one call per event
     ev_of_track = np.repeat(np.arange(b.n_events), np.diff(b.velo_offsets.astype(np.int64)))
@@ -707,6 +717,13 @@ def bench_fitgrad(args, dev):
             "fwd_only_tracks_per_s": round(n / (ms_f * 1e-3), 1), "fwd_only_ms": round(ms_f, 5),
             "fwd_bwd_algorithmic_GBps": round(bytes_fb / (ms_fb * 1e-3) / 1e9, 1),
             "rotated_copies": R,
+            "frozen_layout": {"fwd_bwd_tracks_per_s": round(n / (ms_fz * 1e-3), 1),
+                              "fwd_bwd_ms": round(ms_fz, 5),
+                              "algorithmic_GBps": round((n * (16 + 4 + 40 + 8) + 2 * 4 * (4 * S)) /
+                                                        (ms_fz * 1e-3) / 1e9, 1),
+                              "freeze_ms": round(ms_freeze, 5),
+                              "what": "compass_fit_grad_frozen on u, weight and sector gathered once per "
+                                      "track by compass_fit_freeze (same results)"},
             "per_event_launch_tracks_per_s": round(n / (ms_pe * 1e-3), 1) if ms_pe else None,
             "per_event_launch_ms": round(ms_pe, 3) if ms_pe else None,
             "per_event_what": "compass_fit_grad fwd+bwd, one call per event (the offset gradient of "

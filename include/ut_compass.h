@@ -195,6 +195,29 @@ utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks, const in
                             hipStream_t stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * compass_fit_freeze / compass_fit_grad_frozen — the same fit chi2 and adjoint as compass_fit_grad
+ * (same formulas, same roundings, the same results bit for bit), with the frozen hits gathered
+ * once into track-major form: compass_fit_freeze writes, for every track t and layer l, the u,
+ * weight and global sector l*S+s of its layer-l hit to track_u[4t+l], track_weight[4t+l] and
+ * track_sector[4t+l] (0, 0 and -1 for a slot that compass_fit_grad skips); compass_fit_grad_frozen
+ * then reads 40 bytes per track instead of gathering from the hit arrays, and skips slots whose
+ * sector is outside [0, 4S).  track_u and track_weight must be 16-byte aligned and track_sector
+ * 8-byte aligned (UTC_ERR_ARG otherwise).  Outputs, workspace and errors as compass_fit_grad.
+ * --------------------------------------------------------------------------------------------- */
+utc_status compass_fit_freeze(const utc_geometry* geom, int64_t n_tracks, const int32_t* track_hit_idx,
+                              int64_t n_hits, const float* hit_u, const float* hit_weight,
+                              const uint32_t* hit_lhcbid, float* track_u, float* track_weight,
+                              int16_t* track_sector, hipStream_t stream);
+
+utc_status compass_fit_grad_frozen(const utc_geometry* geom, int64_t n_tracks, const float* track_u,
+                                   const float* track_weight, const int16_t* track_sector,
+                                   const float* vx, const float* vy, const float* vtx,
+                                   const float* vty, const float* qop, const float* offsets,
+                                   float grad_scale, float* chi2_track, double* chi2_total,
+                                   float* grad_qop, float* grad_offsets, void* workspace,
+                                   size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Autotuning of the batched launch (not in the paper, which tuned its kernel parameters by hand,
  * Section VI-C).  Each call runs the matching entry point on the caller's buffers (same arguments
  * and meaning as ut_decode / compass_find) for every candidate launch shape: window tile in

@@ -73,6 +73,11 @@ def library():
     L.compass_fit_grad.restype = ctypes.c_int
     L.compass_fit_grad.argtypes = [_P, _i64, _P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _f, _P,
                                    _P, _P, _P, _P, _sz, _P]
+    L.compass_fit_freeze.restype = ctypes.c_int
+    L.compass_fit_freeze.argtypes = [_P, _i64, _P, _i64, _P, _P, _P, _P, _P, _P, _P]
+    L.compass_fit_grad_frozen.restype = ctypes.c_int
+    L.compass_fit_grad_frozen.argtypes = [_P, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _f, _P, _P,
+                                          _P, _P, _P, _sz, _P]
     for name in ("ut_decode_autotune", "compass_find_autotune"):
         getattr(L, name).restype = ctypes.c_int
     L.ut_decode_autotune.argtypes = [_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -306,6 +311,56 @@ def _fit_grad_workspace(geom: Geometry, device):
     if key not in cache:
         cache[key] = _workspace(library().compass_fit_grad_workspace_bytes(geom.n_sectors), device)
     return cache[key]
+
+
+def compass_fit_freeze(geom: Geometry, track_hit_idx, hit_u, hit_weight, hit_lhcbid, out=None,
+                       stream=None):
+    """The frozen hits of the fits in track-major form (u, weight, global sector per layer).
+    Returns dict(track_u, track_weight, track_sector) of shape (n, 4)."""
+    L = library()
+    dev = hit_u.device
+    n = int(track_hit_idx.shape[0])
+    if out is None:
+        out = dict(track_u=torch.empty((n, 4), dtype=torch.float32, device=dev),
+                   track_weight=torch.empty((n, 4), dtype=torch.float32, device=dev),
+                   track_sector=torch.empty((n, 4), dtype=torch.int16, device=dev))
+    st = L.compass_fit_freeze(geom.ref, n, _ptr(track_hit_idx, "i32"), int(hit_u.shape[0]),
+                              _ptr(hit_u, "f32"), _ptr(hit_weight, "f32"), _ptr(hit_lhcbid, "i32"),
+                              _ptr(out["track_u"], "f32"), _ptr(out["track_weight"], "f32"),
+                              _ptr(out["track_sector"], "i16"), _stream(stream))
+    _check(st, "compass_fit_freeze")
+    return out
+
+
+def compass_fit_grad_frozen(geom: Geometry, frozen, vx, vy, vtx, vty, qop, offsets,
+                            grad_scale: float = 1.0, want_grad: bool = True,
+                            want_chi2_track: bool = True, out=None, workspace=None, stream=None):
+    """compass_fit_grad on hits frozen by compass_fit_freeze (same results)."""
+    L = library()
+    dev = qop.device
+    n = int(qop.shape[0])
+    S = geom.n_sectors
+    if out is None:
+        out = dict(chi2_total=torch.empty(1, dtype=torch.float64, device=dev))
+        if want_chi2_track:
+            out["chi2_track"] = torch.empty(n, dtype=torch.float32, device=dev)
+        if want_grad:
+            out["grad_qop"] = torch.empty(n, dtype=torch.float32, device=dev)
+            out["grad_offsets"] = torch.empty(4 * S, dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = _workspace(L.compass_fit_grad_workspace_bytes(S), dev)
+    st = L.compass_fit_grad_frozen(geom.ref, n, _ptr(frozen["track_u"], "f32"),
+                                   _ptr(frozen["track_weight"], "f32"),
+                                   _ptr(frozen["track_sector"], "i16"), _ptr(vx, "f32"),
+                                   _ptr(vy, "f32"), _ptr(vtx, "f32"), _ptr(vty, "f32"),
+                                   _ptr(qop, "f32"), _ptr(offsets, "f32"), float(grad_scale),
+                                   _ptr(out.get("chi2_track"), "f32"),
+                                   _ptr(out.get("chi2_total"), "f64"),
+                                   _ptr(out.get("grad_qop"), "f32"),
+                                   _ptr(out.get("grad_offsets"), "f32"), _ptr(workspace),
+                                   workspace.numel(), _stream(stream))
+    _check(st, "compass_fit_grad_frozen")
+    return out
 
 
 class CompassChi2Function(torch.autograd.Function):

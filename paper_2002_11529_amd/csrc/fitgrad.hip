@@ -32,11 +32,44 @@ __device__ inline double from_fixed(uint64_t hi, uint64_t lo) {
 // pairs of the 4S sector sums and, last, of the total chi2.  The sums are accumulated in LDS when
 // they fit (kLdsAcc), else with integer atomics directly in the workgroup's own column, cleared
 // beforehand by k_fitgrad_clear; either way a workgroup writes its own column and nothing else.
-template <bool kLdsAcc>
+// The hits of the frozen fits, either gathered through the hit indices from the hit arrays, or
+// already in track-major form (compass_fit_freeze): u, weight and global sector of the four layers
+// of each track, 40 bytes per track read as three vectors.
+struct FitHits {
+  const int32_t* idx;        // [4n] hit indices (gathered form)
+  int64_t n_hits;
+  const float* u;            // hit arrays (gathered form)
+  const float* w;
+  const uint32_t* id;
+  const float4* tu;          // [n] per-track u (frozen form)
+  const float4* tw;          // [n] per-track weights
+  const short4* ts;          // [n] per-track global sectors, -1 = no hit
+};
+
+// Layer-l hit of track t: its u, weight and global sector, or false when the slot holds no hit.
+template <bool kFrozen>
+__device__ inline bool fit_hit(const Geom& g, const FitHits& h, int64_t t, int l, const float4& tu,
+                               const float4& tw, const short4& ts, float& u, float& w, int& sec) {
+  if constexpr (kFrozen) {
+    sec = l == 0 ? ts.x : l == 1 ? ts.y : l == 2 ? ts.z : ts.w;
+    u = l == 0 ? tu.x : l == 1 ? tu.y : l == 2 ? tu.z : tu.w;
+    w = l == 0 ? tw.x : l == 1 ? tw.y : l == 2 ? tw.z : tw.w;
+    return sec >= 0 && sec < kLayers * g.S;
+  } else {
+    const int32_t hi = h.idx[t * kLayers + l];
+    if (hi < 0 || hi >= h.n_hits) return false;
+    const uint32_t id = h.id[hi];
+    if ((id >> 28) >= (uint32_t)kLayers || ((id >> 12) & 0xFFFFu) >= (uint32_t)g.S) return false;
+    sec = (int)(id >> 28) * g.S + (int)((id >> 12) & 0xFFFFu);
+    u = h.u[hi];
+    w = h.w[hi];
+    return true;
+  }
+}
+
+template <bool kLdsAcc, bool kFrozen>
 __global__ void __launch_bounds__(1024)
-k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, int64_t n_hits,
-          const float* __restrict__ hu, const float* __restrict__ hw,
-          const uint32_t* __restrict__ hid, const float* __restrict__ vx,
+k_fitgrad(Geom g, int64_t n_tracks, FitHits fh, const float* __restrict__ vx,
           const float* __restrict__ vy, const float* __restrict__ vtx,
           const float* __restrict__ vty, const float* __restrict__ qop,
           const float* __restrict__ offsets, float m2s, float* __restrict__ chi2_track,
@@ -63,19 +96,24 @@ k_fitgrad(Geom g, int64_t n_tracks, const int32_t* __restrict__ track_hit_idx, i
        t += (int64_t)gridDim.x * blockDim.x) {
     const double x0 = vx[t], y0 = vy[t], tx = vtx[t], ty = vty[t];
     const double q = qop[t];
+    float4 tu{}, tw{};
+    short4 ts{};
+    if constexpr (kFrozen) {
+      tu = fh.tu[t];
+      tw = fh.tw[t];
+      ts = fh.ts[t];
+    }
     float c2 = 0.0f, gq = 0.0f;
 #pragma unroll
     for (int l = 0; l < kLayers; ++l) {
-      const int32_t h = track_hit_idx[t * kLayers + l];
-      if (h < 0 || h >= n_hits) continue;
-      const uint32_t id = hid[h];
-      if ((id >> 28) >= (uint32_t)kLayers || ((id >> 12) & 0xFFFFu) >= (uint32_t)S) continue;
-      const int sec = (int)(id >> 28) * S + (int)((id >> 12) & 0xFFFFu);
+      float hu, hw;
+      int sec;
+      if (!fit_hit<kFrozen>(g, fh, t, l, tu, tw, ts, hu, hw, sec)) continue;
       const double xs = x0 + tx * dz[l];
       const double yl = y0 + ty * dz[l];
-      const double m = (double)hu[h] + yl * (double)g.dxdy[l];
+      const double m = (double)hu + yl * (double)g.dxdy[l];
       const float r = (float)(((m - (double)offsets[sec]) - xs) - (double)g.a_kick[l] * q);
-      const float wr = hw[h] * r;
+      const float wr = hw * r;
       c2 = c2 + wr * r;
       gq = gq + wr * g.a_kick[l];
       if (want_sums) {
@@ -157,22 +195,16 @@ extern "C" size_t compass_fit_grad_workspace_bytes(int32_t n_sectors)
   return (n + 255) / 256 * 256;
 }
 
-extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks,
-                                       const int32_t* track_hit_idx, int64_t n_hits,
-                                       const float* hit_u, const float* hit_weight,
-                                       const uint32_t* hit_lhcbid,
-                                       const float* vx, const float* vy, const float* vtx,
-                                       const float* vty, const float* qop, const float* offsets,
-                                       float grad_scale, float* chi2_track, double* chi2_total,
-                                       float* grad_qop, float* grad_offsets, void* workspace,
-                                       size_t workspace_bytes, hipStream_t stream)
+// Checks, launches and the sum finalisation shared by compass_fit_grad and compass_fit_grad_frozen.
+template <bool kFrozen>
+static utc_status fit_grad_launch(const utc_geometry* geom, int64_t n_tracks, const FitHits& fh,
+                                  const float* vx, const float* vy, const float* vtx, const float* vty,
+                                  const float* qop, const float* offsets, float grad_scale,
+                                  float* chi2_track, double* chi2_total, float* grad_qop,
+                                  float* grad_offsets, void* workspace, size_t workspace_bytes,
+                                  hipStream_t stream)
 {
-  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
-      n_tracks < 0 || n_hits < 0)
-    return UTC_ERR_ARG;
-  if (n_tracks > 0 && (!track_hit_idx || !hit_u || !hit_weight || !hit_lhcbid || !vx || !vy ||
-                       !vtx || !vty || !qop || !offsets))
-    return UTC_ERR_ARG;
+  if (n_tracks > 0 && (!vx || !vy || !vtx || !vty || !qop || !offsets)) return UTC_ERR_ARG;
   if (!workspace || workspace_bytes < compass_fit_grad_workspace_bytes(geom->n_sectors))
     return UTC_ERR_WORKSPACE;
   const Geom g = make_geom(*geom);
@@ -190,22 +222,121 @@ extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_track
   int64_t blocks = (n_tracks + block - 1) / block;
   if (blocks > kMaxRows) blocks = kMaxRows;
   if (blocks < 1) blocks = 1;
-  if (lds_acc && !allow_dynamic_lds(reinterpret_cast<const void*>(k_fitgrad<true>), lds)) return UTC_ERR_HIP;
+  if (lds_acc && !allow_dynamic_lds(reinterpret_cast<const void*>(k_fitgrad<true, kFrozen>), lds))
+    return UTC_ERR_HIP;
   if (want_sums && !lds_acc) {
     const int64_t n = 2 * (int64_t)n_sums * blocks;
     hipLaunchKernelGGL(k_fitgrad_clear, dim3((unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096)),
                        dim3(256), 0, stream, part, n);
   }
   if (lds_acc)
-    hipLaunchKernelGGL(k_fitgrad<true>, dim3((unsigned)blocks), dim3(block), lds, stream, g, n_tracks,
-                       track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop,
-                       offsets, m2s, chi2_track, grad_qop, want_sums, part);
+    hipLaunchKernelGGL((k_fitgrad<true, kFrozen>), dim3((unsigned)blocks), dim3(block), lds, stream, g,
+                       n_tracks, fh, vx, vy, vtx, vty, qop, offsets, m2s, chi2_track, grad_qop,
+                       want_sums, part);
   else
-    hipLaunchKernelGGL(k_fitgrad<false>, dim3((unsigned)blocks), dim3(block), 0, stream, g, n_tracks,
-                       track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, vx, vy, vtx, vty, qop,
-                       offsets, m2s, chi2_track, grad_qop, want_sums, part);
+    hipLaunchKernelGGL((k_fitgrad<false, kFrozen>), dim3((unsigned)blocks), dim3(block), 0, stream, g,
+                       n_tracks, fh, vx, vy, vtx, vty, qop, offsets, m2s, chi2_track, grad_qop,
+                       want_sums, part);
   if (want_sums)
     hipLaunchKernelGGL(k_fitgrad_finalize, dim3((n_sums + 3) / 4), dim3(256), 0, stream, part,
                        (int)blocks, n_sums, -2.0 * (double)grad_scale, grad_offsets, chi2_total);
   return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
+}
+
+extern "C" utc_status compass_fit_grad(const utc_geometry* geom, int64_t n_tracks,
+                                       const int32_t* track_hit_idx, int64_t n_hits,
+                                       const float* hit_u, const float* hit_weight,
+                                       const uint32_t* hit_lhcbid,
+                                       const float* vx, const float* vy, const float* vtx,
+                                       const float* vty, const float* qop, const float* offsets,
+                                       float grad_scale, float* chi2_track, double* chi2_total,
+                                       float* grad_qop, float* grad_offsets, void* workspace,
+                                       size_t workspace_bytes, hipStream_t stream)
+{
+  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
+      n_tracks < 0 || n_hits < 0)
+    return UTC_ERR_ARG;
+  if (n_tracks > 0 && (!track_hit_idx || !hit_u || !hit_weight || !hit_lhcbid)) return UTC_ERR_ARG;
+  FitHits fh{track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, nullptr, nullptr, nullptr};
+  return fit_grad_launch<false>(geom, n_tracks, fh, vx, vy, vtx, vty, qop, offsets, grad_scale,
+                                chi2_track, chi2_total, grad_qop, grad_offsets, workspace,
+                                workspace_bytes, stream);
+}
+
+// One thread per track: the u, weight and global sector of its four hits, as compass_fit_grad
+// reads them, written track-major.
+__global__ void k_fit_freeze(Geom g, int64_t n_tracks, FitHits fh, float4* __restrict__ tu,
+                             float4* __restrict__ tw, short4* __restrict__ ts)
+{
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tracks;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    float u[kLayers], w[kLayers];
+    int sec[kLayers];
+    const float4 z4{};
+    const short4 s4{};
+#pragma unroll
+    for (int l = 0; l < kLayers; ++l) {
+      if (!fit_hit<false>(g, fh, t, l, z4, z4, s4, u[l], w[l], sec[l])) {
+        u[l] = 0.0f;
+        w[l] = 0.0f;
+        sec[l] = -1;
+      }
+    }
+    tu[t] = make_float4(u[0], u[1], u[2], u[3]);
+    tw[t] = make_float4(w[0], w[1], w[2], w[3]);
+    ts[t] = make_short4((short)sec[0], (short)sec[1], (short)sec[2], (short)sec[3]);
+  }
+}
+
+extern "C" utc_status compass_fit_freeze(const utc_geometry* geom, int64_t n_tracks,
+                                         const int32_t* track_hit_idx, int64_t n_hits,
+                                         const float* hit_u, const float* hit_weight,
+                                         const uint32_t* hit_lhcbid, float* track_u,
+                                         float* track_weight, int16_t* track_sector,
+                                         hipStream_t stream)
+{
+  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
+      n_tracks < 0 || n_hits < 0)
+    return UTC_ERR_ARG;
+  if (n_tracks > 0 && (!track_hit_idx || !hit_u || !hit_weight || !hit_lhcbid || !track_u ||
+                       !track_weight || !track_sector))
+    return UTC_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(track_u) | reinterpret_cast<uintptr_t>(track_weight)) & 15u ||
+      reinterpret_cast<uintptr_t>(track_sector) & 7u)
+    return UTC_ERR_ARG;
+  if (n_tracks == 0) return UTC_OK;
+  (void)hipGetLastError();
+  const Geom g = make_geom(*geom);
+  FitHits fh{track_hit_idx, n_hits, hit_u, hit_weight, hit_lhcbid, nullptr, nullptr, nullptr};
+  int64_t blocks = (n_tracks + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fit_freeze, dim3((unsigned)blocks), dim3(256), 0, stream, g, n_tracks, fh,
+                     reinterpret_cast<float4*>(track_u), reinterpret_cast<float4*>(track_weight),
+                     reinterpret_cast<short4*>(track_sector));
+  return hipGetLastError() == hipSuccess ? UTC_OK : UTC_ERR_HIP;
+}
+
+extern "C" utc_status compass_fit_grad_frozen(const utc_geometry* geom, int64_t n_tracks,
+                                              const float* track_u, const float* track_weight,
+                                              const int16_t* track_sector,
+                                              const float* vx, const float* vy, const float* vtx,
+                                              const float* vty, const float* qop,
+                                              const float* offsets, float grad_scale,
+                                              float* chi2_track, double* chi2_total,
+                                              float* grad_qop, float* grad_offsets,
+                                              void* workspace, size_t workspace_bytes,
+                                              hipStream_t stream)
+{
+  if (!geom || geom->n_layers != kLayers || geom->n_sectors < 1 || geom->n_sectors > 8192 ||
+      n_tracks < 0)
+    return UTC_ERR_ARG;
+  if (n_tracks > 0 && (!track_u || !track_weight || !track_sector)) return UTC_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(track_u) | reinterpret_cast<uintptr_t>(track_weight)) & 15u ||
+      reinterpret_cast<uintptr_t>(track_sector) & 7u)
+    return UTC_ERR_ARG;
+  FitHits fh{nullptr, 0, nullptr, nullptr, nullptr, reinterpret_cast<const float4*>(track_u),
+             reinterpret_cast<const float4*>(track_weight), reinterpret_cast<const short4*>(track_sector)};
+  return fit_grad_launch<true>(geom, n_tracks, fh, vx, vy, vtx, vty, qop, offsets, grad_scale,
+                               chi2_track, chi2_total, grad_qop, grad_offsets, workspace,
+                               workspace_bytes, stream);
 }

@@ -138,3 +138,28 @@ def test_autograd_function(frozen):
     assert float(chi2.detach()) == ref["chi2_total"][0]
     assert np.allclose(qd.grad.cpu().numpy(), ref["grad_qop"], rtol=1e-6, atol=0)
     assert np.allclose(od.grad.cpu().numpy(), ref["grad_offsets"], rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_frozen_layout_equals_gathered(frozen, seed):
+    """compass_fit_freeze + compass_fit_grad_frozen give the gathered call's results bit for bit,
+    including tracks with 3 hits and slots that the gathered call skips (index -1, out of range)."""
+    fr = frozen
+    F = fr["F"]
+    q, off = _point(fr, seed)
+    qd, od = torch.from_numpy(q).to(DEV), torch.from_numpy(off).to(DEV)
+    idx = F["track_hit_idx"].clone()
+    n = int(idx.shape[0])
+    # a few slots the gathered call skips
+    idx[5, 1] = -1
+    idx[7, 2] = int(F["hit_u"].shape[0]) + 3
+    ref = utc.compass_fit_grad(fr["geom"], idx, F["hit_u"], F["hit_weight"], F["hit_lhcbid"], F["vx"],
+                               F["vy"], F["vtx"], F["vty"], qd, od)
+    fz = utc.compass_fit_freeze(fr["geom"], idx, F["hit_u"], F["hit_weight"], F["hit_lhcbid"])
+    got = utc.compass_fit_grad_frozen(fr["geom"], fz, F["vx"], F["vy"], F["vtx"], F["vty"], qd, od)
+    torch.cuda.synchronize()
+    ts = fz["track_sector"].cpu().numpy()
+    assert ts[5, 1] == -1 and ts[7, 2] == -1 and (ts[:, 0] >= 0).sum() > 0.9 * n
+    for k in ("chi2_track", "grad_qop", "grad_offsets", "chi2_total"):
+        a, e = got[k].cpu().numpy(), ref[k].cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), e.view(np.uint8)), k

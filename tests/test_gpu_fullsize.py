@@ -165,8 +165,15 @@ def test_fitgrad_full_million_tracks():
     g = utc.compass_fit_grad(geom, res["hit_idx"][kd].contiguous(), hits["u"], hits["weight"],
                              hits["lhcbid"], *(v[kd].contiguous() for v in dv["vel"]),
                              torch.from_numpy(q).to(DEV), torch.from_numpy(off).to(DEV))
+    # the same fits on the hits frozen in track-major form: identical results
+    fz = utc.compass_fit_freeze(geom, res["hit_idx"][kd].contiguous(), hits["u"], hits["weight"],
+                                hits["lhcbid"])
+    g2 = utc.compass_fit_grad_frozen(geom, fz, *(v[kd].contiguous() for v in dv["vel"]),
+                                     torch.from_numpy(q).to(DEV), torch.from_numpy(off).to(DEV))
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in g.items()}
+    for k, v in g2.items():
+        assert np.array_equal(v.cpu().numpy().view(np.uint8), g[k].view(np.uint8)), k
     args = (b.detector, c["hit_idx"][keep], d["u"], d["weight"], d["lhcbid"], b.velo_x[keep],
             b.velo_y[keep], b.velo_tx[keep], b.velo_ty[keep])
     o = oracle.fit_grad(*args, q, off, precision="f32")
