@@ -4,7 +4,7 @@
 // function of the per-sector x offsets delta and the per-track q/p.  One thread per track computes
 // its chi2 and d chi2/d qop directly; the per-sector sums of w*r and the total chi2 are accumulated
 // exactly as integers in units of 2^-40 (a hi/lo pair of 64-bit words per sum), first in LDS per
-// workgroup, then as one column of partial sums per workgroup that a second kernel adds up, so the
+// workgroup, then as one row of partial sums per workgroup that a second kernel adds up, so the
 // result is the same for every schedule and launch shape.
 #include "common.hpp"
 
@@ -28,10 +28,6 @@ __device__ inline double from_fixed(uint64_t hi, uint64_t lo) {
   return ((double)(int64_t)hi * kTwo32 + (double)lo) / kFix;
 }
 
-// Per-workgroup partial sums: workgroup b writes column b of part[2*(4S+1)][grid], the (hi, lo)
-// pairs of the 4S sector sums and, last, of the total chi2.  The sums are accumulated in LDS when
-// they fit (kLdsAcc), else with integer atomics directly in the workgroup's own column, cleared
-// beforehand by k_fitgrad_clear; either way a workgroup writes its own column and nothing else.
 // The hits of the frozen fits, either gathered through the hit indices from the hit arrays, or
 // already in track-major form (compass_fit_freeze): u, weight and global sector of the four layers
 // of each track, 40 bytes per track read as three vectors.
@@ -67,6 +63,10 @@ __device__ inline bool fit_hit(const Geom& g, const FitHits& h, int64_t t, int l
   }
 }
 
+// Per-workgroup partial sums: workgroup b writes row b of part[grid][2*(4S+1)], the (hi, lo)
+// pairs of the 4S sector sums and, last, of the total chi2.  The sums are accumulated in LDS when
+// they fit (kLdsAcc), else with integer atomics directly in the workgroup's own row, cleared
+// beforehand by k_fitgrad_clear; either way a workgroup writes its own row and nothing else.
 template <bool kLdsAcc, bool kFrozen>
 __global__ void __launch_bounds__(1024)
 k_fitgrad(Geom g, int64_t n_tracks, FitHits fh, const float* __restrict__ vx,
@@ -78,10 +78,10 @@ k_fitgrad(Geom g, int64_t n_tracks, FitHits fh, const float* __restrict__ vx,
   extern __shared__ uint64_t s_acc[];  // [2 * (4S + 1)] when want_sums and kLdsAcc
   const int S = g.S;
   const int n_sums = kLayers * S + 1;
-  uint64_t* col = part + blockIdx.x;   // this workgroup's column, stride gridDim.x
+  uint64_t* col = part + (size_t)blockIdx.x * 2 * n_sums;   // this workgroup's row (contiguous)
   auto acc_add = [&](int i, uint64_t v) {
     if constexpr (kLdsAcc) atomicAdd((unsigned long long*)&s_acc[i], (unsigned long long)v);
-    else atomicAdd((unsigned long long*)&col[(size_t)i * gridDim.x], (unsigned long long)v);
+    else atomicAdd((unsigned long long*)&col[i], (unsigned long long)v);
   };
   if (kLdsAcc && want_sums) {
     for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x) s_acc[i] = 0;
@@ -145,12 +145,12 @@ k_fitgrad(Geom g, int64_t n_tracks, FitHits fh, const float* __restrict__ vx,
   }
   if constexpr (!kLdsAcc) return;
   __syncthreads();
-  // column blockIdx.x of the sum-major partial array part[2*n_sums][gridDim.x]
+  // row blockIdx.x of the workgroup-major partial array part[gridDim.x][2*n_sums], written whole
   for (int i = threadIdx.x; i < 2 * n_sums; i += blockDim.x)
-    col[(size_t)i * gridDim.x] = s_acc[i];
+    col[i] = s_acc[i];
 }
 
-// Zeroes n words (the partial columns when they are accumulated in place).
+// Zeroes n words (the partial rows when they are accumulated in place).
 __global__ void k_fitgrad_clear(uint64_t* __restrict__ part, int64_t n)
 {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -167,8 +167,8 @@ __global__ void k_fitgrad_finalize(const uint64_t* __restrict__ part, int n_rows
   const int lane = lane_id();
   uint64_t hi = 0, lo = 0;
   for (int r = lane; r < n_rows; r += kWave) {
-    hi += part[(size_t)(2 * i) * n_rows + r];
-    lo += part[(size_t)(2 * i + 1) * n_rows + r];
+    hi += part[(size_t)r * 2 * n_sums + 2 * i];
+    lo += part[(size_t)r * 2 * n_sums + 2 * i + 1];
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -213,7 +213,7 @@ static utc_status fit_grad_launch(const utc_geometry* geom, int64_t n_tracks, co
   uint64_t* part = static_cast<uint64_t*>(workspace);
   const bool want_sums = grad_offsets != nullptr || chi2_total != nullptr;
   const float m2s = -2.0f * grad_scale;
-  // the sums in LDS when they fit (up to 2559 sectors per layer), else in the workspace columns
+  // the sums in LDS when they fit (up to 2559 sectors per layer), else in the workspace rows
   const size_t lds_need = want_sums ? 2 * (size_t)n_sums * sizeof(uint64_t) : 0;
   const bool lds_acc = lds_need <= 160 * 1024;
   const size_t lds = lds_acc ? lds_need : 0;
