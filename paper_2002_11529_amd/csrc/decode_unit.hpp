@@ -126,6 +126,9 @@ __device__ inline UnitCount unit_count(const Geom& g, const uint16_t* __restrict
     const uint32_t w0 = ws.off[0];
     const uint32_t nw = ws.off[S] - w0;
     st.staged = ws.raw != nullptr && nw <= (uint32_t)ws.cap;
+    // the decoding kernel (ws.raw set) needs the words here only to stage them: a unit that does
+    // not fit is read chunk by chunk later, and its hit count comes from the counting kernel
+    if (ws.raw != nullptr && !st.staged) return st;
     uint32_t c = 0;
     if ((reinterpret_cast<uintptr_t>(words) & 15u) == 0) {
       // 16-byte loads of 8 words per lane from the aligned word at or before w0
@@ -210,29 +213,46 @@ __device__ inline void store_hit(const Geom& g, float z, const DecodedHit& d, in
   out.weight[h] = d.w;
 }
 
-// A bank too large for the LDS chunk: rank every hit against the whole bank in global memory.
+// A bank too large for the LDS chunk: every hit (64 at a time, in bank order) is ranked against the
+// whole bank, whose words pass through LDS a chunk at a time (ws.raw is free here: a unit with such a
+// bank is never staged whole).  O(n^2 / 64) LDS compares per wavefront for a bank of n words.
 __device__ inline uint32_t big_bank(const Geom& g, const uint16_t* __restrict__ words, int layer,
                                     uint32_t s, uint32_t a, uint32_t n, int64_t first_hit,
-                                    int64_t capacity, const HitsOut& out, uint32_t* flags)
+                                    int64_t capacity, const WaveScratch& ws, const HitsOut& out,
+                                    uint32_t* flags)
 {
   const int lane = lane_id();
   const float z_l = g.z_layer[layer];
+  const uint32_t cap = (uint32_t)ws.cap & ~3u;
   uint32_t nh = 0;
   for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
     const uint32_t i = i0 + lane;
-    const uint16_t v = i < n ? words[a + i] : (uint16_t)0;
-    nh += (uint32_t)__popcll(ballot((v & 0xFu) != 0u));
-  }
-  for (uint32_t i = lane; i < n; i += kWave) {
-    const uint16_t v = words[a + i];
-    if (!(v & 0xFu)) continue;
+    const uint32_t v = i < n ? (uint32_t)words[a + i] : 0u;
+    const bool valid = (v & 0xFu) != 0u;
+    nh += (uint32_t)__popcll(ballot(valid));
     uint32_t rank = 0;
-    for (uint32_t j = 0; j < n; ++j) {
-      const uint16_t o = words[a + j];
-      rank += ((o & 0xFu) != 0u) & ((o < v) | ((o == v) & (j < i)));
+    for (uint32_t t0 = 0; t0 < n; t0 += cap) {
+      const uint32_t tn = min(cap, n - t0);
+      wave_sync();   // the previous tile is no longer read
+      for (uint32_t k = lane; k < tn; k += kWave) ws.raw[k] = words[a + t0 + k];
+      for (uint32_t k = tn + lane; k < ((tn + 3u) & ~3u); k += kWave) ws.raw[k] = 0;   // padding
+      wave_sync();
+      if (valid) {
+        // a word o of the bank at position p comes before this hit when it is valid and
+        // (o, p) < (v, i); two words per 4-byte LDS read (ws.raw is 4-byte aligned)
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(ws.raw);
+        for (uint32_t j = 0; j < tn; j += 4) {
+          const uint32_t p0 = q[j >> 1], p1 = q[(j >> 1) + 1];
+          const uint32_t o[4] = {p0 & 0xFFFFu, p0 >> 16, p1 & 0xFFFFu, p1 >> 16};
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const uint32_t pos = t0 + j + (uint32_t)h;
+            rank += (uint32_t)(((o[h] & 0xFu) != 0u) & ((o[h] < v) | ((o[h] == v) & (pos < i))));
+          }
+        }
+      }
     }
-    const DecodedHit d = decode_word(g, layer, s, v);
-    store_hit(g, z_l, d, first_hit + rank, capacity, out, flags);
+    if (valid) store_hit(g, z_l, decode_word(g, layer, s, v), first_hit + rank, capacity, out, flags);
   }
   return nh;
 }
@@ -317,7 +337,7 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
     }
     if (c1 == c0) {
       if (lane == 0) hit_offsets[b0 + c0] = base + local;
-      local += big_bank(g, words, layer, (uint32_t)c0, a0, e0 - a0, (int64_t)base + local, capacity,
+      local += big_bank(g, words, layer, (uint32_t)c0, a0, e0 - a0, (int64_t)base + local, capacity, ws,
                         out, flags);
       wave_sync();
       ++c0;

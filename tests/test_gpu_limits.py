@@ -51,8 +51,8 @@ def test_largest_geometry(max_hits):
 
 
 def test_bank_of_the_largest_size():
-    """A bank of exactly UTC_MAX_BANK_WORDS words is decoded (sorted against the whole bank in
-    global memory), not flagged."""
+    """A bank of exactly UTC_MAX_BANK_WORDS words is decoded (ranked against the whole bank a chunk
+    at a time through LDS), not flagged."""
     b = synth.generate("tiny", n_events=2, seed=33, with_truth=False)
     S = b.detector.n_sectors
     bank = (1 * 4 + 2) * S + 7          # event 1, layer 2, sector 7
@@ -70,6 +70,30 @@ def test_bank_of_the_largest_size():
     assert int(off[bank + 1] - off[bank]) == MAX_BANK_WORDS
     print(f"[limits bank] words={b.n_words}", flush=True)
     _check(b)
+
+
+@pytest.mark.parametrize("n_extra,tile", [(1500, 0), (700, 4), (3000, 6)])
+def test_banks_larger_than_the_lds_chunk(n_extra, tile):
+    """Banks with more words than the decoder's LDS chunk (about 900 words at the default tile, a
+    few hundred at small tiles) are ranked a chunk at a time through LDS; several such banks in one
+    unit, duplicated words (ties keep bank order), padding in between."""
+    b = synth.generate("tiny", n_events=3, seed=35, with_truth=False)
+    S = b.detector.n_sectors
+    rng = np.random.default_rng(n_extra)
+    for bank in ((2 * 4 + 1) * S + 12, (2 * 4 + 1) * S + 17, (0 * 4 + 3) * S + 3):
+        off = b.bank_offsets.astype(np.int64)
+        strip = rng.integers(0, 64, n_extra)          # few distinct positions: many equal words
+        frac = rng.integers(0, 8, n_extra)
+        size = np.where(rng.random(n_extra) < 0.1, 0, rng.integers(1, 4, n_extra))
+        extra = ((strip << 7) | (frac << 4) | size).astype(np.uint16)
+        b.words = np.concatenate([b.words[:off[bank + 1]], extra, b.words[off[bank + 1]:]])
+        off[bank + 1:] += n_extra
+        b.bank_offsets = off.astype(np.uint32)
+    print(f"[limits large banks] extra={n_extra} tile={tile} words={b.n_words}", flush=True)
+    h, r, *_ = gpu_run(b, launch_decode=dict(block=256, grid=0, tile=tile), find=False)
+    d, c = oracle_run(b, find=False)
+    assert d["flags"] == 0 and h["error_flags"] == 0
+    assert_decode_equal(h, d)
 
 
 def test_layer_beyond_16_bit_windows():
