@@ -271,11 +271,12 @@ __device__ inline uint32_t count_below(const uint32_t* k, uint32_t mine) {
 // the whole bank: O(n) rather than O(n^2) per bank.
 constexpr uint32_t kDenseBank = 32;
 
-// Hits [lo, hi) of the chunk (compacted order, keys word << 16 | position in ws.key), all of one
-// bank: each word goes to sorted[lo + its rank in the bank by key].  The chunk's marker array and
-// the bank entries of these hits are no longer needed at this point and serve as arrival slots and
-// the bin-ordered hit list.  Wave-uniform.
-__device__ inline void dense_bank(uint32_t lo, uint32_t hi, const WaveScratch& ws, uint16_t* sorted)
+// Hits [lo, hi) of the chunk (compacted order, keys word << 16 | position in ws.key), all of bank
+// `bank`: each word goes to sorted[lo + its rank in the bank by key].  The chunk's marker array and
+// the bank entries of these hits serve as arrival slots and the bin-ordered hit list meanwhile; the
+// bank entries are restored at the end.  Wave-uniform.
+__device__ inline void dense_bank(uint32_t lo, uint32_t hi, int bank, const WaveScratch& ws,
+                                  uint16_t* sorted)
 {
   const int lane = lane_id();
   uint32_t* bins = ws.bins;      // [kBins + 1]
@@ -304,6 +305,9 @@ __device__ inline void dense_bank(uint32_t lo, uint32_t hi, const WaveScratch& w
     for (uint32_t j = bins[bin]; j < s1; ++j) rank += ws.key[order[lo + j]] < mine;
     sorted[lo + rank] = (uint16_t)(mine >> 16);
   }
+  wave_sync();
+  // the bank entries of these hits again (the write-out reads the bank of each sorted slot there)
+  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave) order[k] = (uint16_t)bank;
   wave_sync();
 }
 
@@ -452,25 +456,15 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       while (dense) {
         const int bd = b0c + (int)__builtin_ctzll(dense);
         dense &= dense - 1;
-        dense_bank(ws.hb[bd], ws.hb[bd + 1], ws, sorted);
+        dense_bank(ws.hb[bd], ws.hb[bd + 1], bd, ws, sorted);
       }
     }
-    // bank of each sorted slot: sorting stays inside the banks, so slot p belongs to the bank b
-    // with hb[b] <= p < hb[b+1] (markers at the banks' first slots, then a running maximum)
-    for (uint32_t i = lane; i < nh; i += kWave) ws.mark[i] = 0;
-    wave_sync();
-    for (int b = c0 + lane; b < c1; b += kWave)
-      if (ws.hb[b + 1] > ws.hb[b]) ws.mark[ws.hb[b]] = (uint16_t)(b + 1);
-    wave_sync();
-    // decode in sorted order and store: the 64 lanes write 64 consecutive hits of each array
-    uint32_t bank_run = 0;
+    // decode in sorted order and store: the 64 lanes write 64 consecutive hits of each array.
+    // Sorting stays inside the banks, so sorted slot p belongs to the bank of compacted hit p.
     for (uint32_t p0 = 0; p0 < nh; p0 += kWave) {
       const uint32_t p = p0 + (uint32_t)lane;
-      uint32_t bk1 = wave_inclusive_max(p < nh ? (uint32_t)ws.mark[p] : 0u);
-      bk1 = bk1 > bank_run ? bk1 : bank_run;
-      bank_run = (uint32_t)__builtin_amdgcn_readlane((int)bk1, kWave - 1);
       if (p < nh) {
-        const uint32_t bk = bk1 - 1u;
+        const uint32_t bk = ws.cbank[p];
         const uint32_t v = sorted[p];
         const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
         DecodedHit d;
