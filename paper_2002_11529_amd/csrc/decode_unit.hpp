@@ -33,7 +33,14 @@ struct WaveScratch {
   int cap;
 };
 
-constexpr int kBins = 64;   // bins of the dense-bank sort: the top 6 bits of the word (8 strips)
+#ifndef UTC_DECODE_BIN_BITS
+#define UTC_DECODE_BIN_BITS 6
+#endif
+// bins of the dense-bank sort: the top kBinBits bits of the word (2^(12 - kBinBits) strips each)
+constexpr int kBinBits = UTC_DECODE_BIN_BITS;
+constexpr int kBins = 1 << kBinBits;
+constexpr int kBinsPerLane = kBins / kWave;
+static_assert(kBins % kWave == 0, "whole bins per lane");
 
 __host__ __device__ inline size_t wave_table_bytes(int S) {
   return 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(float) * ((size_t)S + 16) +
@@ -282,27 +289,48 @@ __device__ inline void dense_bank(uint32_t lo, uint32_t hi, int bank, const Wave
   uint32_t* bins = ws.bins;      // [kBins + 1]
   uint16_t* slot = ws.mark;      // [k] arrival slot of hit k in its bin
   uint16_t* order = ws.cbank;    // [lo + i] i-th hit in bin order
-  bins[lane] = 0u;
+  constexpr int kShift = 32 - kBinBits;
+#pragma unroll
+  for (int q = 0; q < kBinsPerLane; ++q) bins[lane * kBinsPerLane + q] = 0u;
   if (lane == 0) bins[kBins] = 0u;
   wave_sync();
   for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
-    slot[k] = (uint16_t)atomicAdd(&bins[ws.key[k] >> 26], 1u);
+    slot[k] = (uint16_t)atomicAdd(&bins[ws.key[k] >> kShift], 1u);
   wave_sync();
+  // bin starts: each lane scans its kBinsPerLane consecutive bins after a scan of the lane sums
+  uint32_t c[kBinsPerLane], csum = 0;
+#pragma unroll
+  for (int q = 0; q < kBinsPerLane; ++q) {
+    c[q] = bins[lane * kBinsPerLane + q];
+    csum += c[q];
+  }
   uint32_t tot;
-  const uint32_t start = wave_excl_scan(bins[lane], &tot);
+  uint32_t start = wave_excl_scan(csum, &tot);
   wave_sync();
-  bins[lane] = start;
+#pragma unroll
+  for (int q = 0; q < kBinsPerLane; ++q) {
+    bins[lane * kBinsPerLane + q] = start;
+    start += c[q];
+  }
   if (lane == 0) bins[kBins] = tot;
   wave_sync();
   for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
-    order[lo + bins[ws.key[k] >> 26] + slot[k]] = (uint16_t)k;
+    order[lo + bins[ws.key[k] >> kShift] + slot[k]] = (uint16_t)k;
   wave_sync();
   for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave) {
     const uint32_t mine = ws.key[k];
-    const uint32_t bin = mine >> 26;
-    const uint32_t s1 = bins[bin + 1];
-    uint32_t rank = bins[bin];   // hits of the lower bins
-    for (uint32_t j = bins[bin]; j < s1; ++j) rank += ws.key[order[lo + j]] < mine;
+    const uint32_t bin = mine >> kShift;
+    const uint32_t s0 = bins[bin], s1 = bins[bin + 1];
+    uint32_t rank = s0;   // hits of the lower bins
+    // the other hits of the bin, four at a time (their list entries, then their keys, read
+    // together); a slot past the bin stands for the hit itself, which is not below its own key
+    for (uint32_t j = s0; j < s1; j += 4) {
+      uint32_t o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = j + q < s1 ? (uint32_t)order[lo + j + q] : k;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rank += ws.key[o[q]] < mine;
+    }
     sorted[lo + rank] = (uint16_t)(mine >> 16);
   }
   wave_sync();
@@ -335,6 +363,8 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
         continue;
       }
       c1 = e0 - a0 > (uint32_t)ws.cap ? c0 : c0 + 1;
+    } else if (st.staged) {
+      c1 = S;   // the whole unit is in LDS already
     } else {
       // the longest run of banks from c0 whose words fit in the staging buffer
       c1 = (int)first_true(c0 + 1, S + 1, [&](int64_t b) { return ws.off[b] - a0 > (uint32_t)ws.cap; }) - 1;
@@ -394,23 +424,35 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
 
     // stable compaction of the valid words, each with its bank (running maximum of the markers);
     // the marker slot is then reused for the number of valid words before that raw position
+    // (four groups of 64 words per pass, their LDS reads and scans independent)
+    constexpr int kCompactGroups = 4;
     uint32_t run = 0;
     uint32_t bank_carry = 0;
-    for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
-      const uint32_t i = i0 + lane;
-      const uint16_t v = i < n ? ws.raw[i] : (uint16_t)0;
-      const bool valid = (v & 0xFu) != 0u;
-      uint32_t bk = wave_inclusive_max(i < n ? (uint32_t)ws.mark[i] : 0u);
-      bk = bk > bank_carry ? bk : bank_carry;
-      bank_carry = (uint32_t)__builtin_amdgcn_readlane((int)bk, kWave - 1);
-      const uint64_t m = ballot(valid);
-      const uint32_t pos = run + lanes_before(m);
-      if (i < n) ws.mark[i] = (uint16_t)pos;
-      if (valid) {
-        ws.key[pos] = ((uint32_t)v << 16) | pos;
-        ws.cbank[pos] = (uint16_t)(bk - 1);
+    for (uint32_t i0 = 0; i0 < n; i0 += kCompactGroups * kWave) {
+      uint32_t v[kCompactGroups], bk[kCompactGroups];
+#pragma unroll
+      for (int k = 0; k < kCompactGroups; ++k) {
+        const uint32_t i = i0 + (uint32_t)(k * kWave + lane);
+        v[k] = i < n ? (uint32_t)ws.raw[i] : 0u;
+        bk[k] = i < n ? (uint32_t)ws.mark[i] : 0u;
       }
-      run += (uint32_t)__popcll(m);
+#pragma unroll
+      for (int k = 0; k < kCompactGroups; ++k) bk[k] = wave_inclusive_max(bk[k]);
+#pragma unroll
+      for (int k = 0; k < kCompactGroups; ++k) {
+        const uint32_t i = i0 + (uint32_t)(k * kWave + lane);
+        const bool valid = (v[k] & 0xFu) != 0u;
+        const uint32_t b = bk[k] > bank_carry ? bk[k] : bank_carry;
+        bank_carry = (uint32_t)__builtin_amdgcn_readlane((int)b, kWave - 1);
+        const uint64_t m = ballot(valid);
+        const uint32_t pos = run + lanes_before(m);
+        if (i < n) ws.mark[i] = (uint16_t)pos;
+        if (valid) {
+          ws.key[pos] = (v[k] << 16) | pos;
+          ws.cbank[pos] = (uint16_t)(b - 1);
+        }
+        run += (uint32_t)__popcll(m);
+      }
     }
     const uint32_t nh = run;
     wave_sync();
@@ -459,19 +501,35 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
         dense_bank(ws.hb[bd], ws.hb[bd + 1], bd, ws, sorted);
       }
     }
-    // decode in sorted order and store: the 64 lanes write 64 consecutive hits of each array.
-    // Sorting stays inside the banks, so sorted slot p belongs to the bank of compacted hit p.
-    for (uint32_t p0 = 0; p0 < nh; p0 += kWave) {
-      const uint32_t p = p0 + (uint32_t)lane;
-      if (p < nh) {
-        const uint32_t bk = ws.cbank[p];
-        const uint32_t v = sorted[p];
-        const uint32_t frac = (v >> 4) & 7u, strip = v >> 7;
-        DecodedHit d;
-        d.lhcbid = ((uint32_t)layer << 28) | (bk << 12) | (strip << 3) | frac;
-        d.u = fmaf((float)(strip * 8u + frac), g.pitch8, ws.u0[bk]);
-        d.w = ws.wt[v & 0xFu];
-        store_hit(g, z_l, d, (int64_t)base + local + p, capacity, out, flags);
+    // decode in sorted order and store: the 64 lanes write 64 consecutive hits of each array,
+    // four such groups per pass (their LDS reads in flight together).  Sorting stays inside the
+    // banks, so sorted slot p belongs to the bank of compacted hit p.
+    constexpr int kStoreGroups = 4;
+    for (uint32_t p0 = 0; p0 < nh; p0 += kStoreGroups * kWave) {
+      uint32_t bk[kStoreGroups], v[kStoreGroups];
+      float u0[kStoreGroups], w[kStoreGroups];
+#pragma unroll
+      for (int k = 0; k < kStoreGroups; ++k) {
+        const uint32_t p = p0 + (uint32_t)(k * kWave + lane);
+        bk[k] = p < nh ? (uint32_t)ws.cbank[p] : 0u;
+        v[k] = p < nh ? (uint32_t)sorted[p] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < kStoreGroups; ++k) {
+        u0[k] = ws.u0[bk[k]];
+        w[k] = ws.wt[v[k] & 0xFu];
+      }
+#pragma unroll
+      for (int k = 0; k < kStoreGroups; ++k) {
+        const uint32_t p = p0 + (uint32_t)(k * kWave + lane);
+        if (p < nh) {
+          const uint32_t frac = (v[k] >> 4) & 7u, strip = v[k] >> 7;
+          DecodedHit d;
+          d.lhcbid = ((uint32_t)layer << 28) | (bk[k] << 12) | (strip << 3) | frac;
+          d.u = fmaf((float)(strip * 8u + frac), g.pitch8, u0[k]);
+          d.w = w[k];
+          store_hit(g, z_l, d, (int64_t)base + local + p, capacity, out, flags);
+        }
       }
     }
     local += nh;
