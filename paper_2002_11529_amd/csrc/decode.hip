@@ -5,8 +5,9 @@
 //     words);
 //   k_decode_scan: one workgroup scans the unit sums into the first hit of every unit;
 //   k_decode: per unit, words staged in LDS, stable compaction of the valid words (ballot + mbcnt),
-//     local hit offsets of the banks, rank sort of each bank by word value, decode and coalesced
-//     store of the six hit fields.
+//     local hit offsets of the banks, sort inside each bank by word value (a counting sort of the
+//     chunk's hits on per-bank word bins, then a rank inside each bin), decode and coalesced store
+//     of the six hit fields.
 // The paper's seven kernels (count, three-kernel prefix sum, pre-decode, find permutation, decode
 // in order; Table "Kernel configuration for UT decoding") become these two; the order inside a bank
 // is by x (the word value) rather than by y.

@@ -25,26 +25,18 @@ struct WaveScratch {
   uint32_t* hb;     // [S+1] first hit of each bank inside the current chunk
   float* u0;        // [S] bin-0 position of each sector of the unit's layer
   float* wt;        // [16] weight of each cluster size
-  uint32_t* bins;   // [kBins+1] bin counters / starts of the dense-bank sort
-  uint16_t* raw;    // [cap] staged raw words, then the chunk's words in sorted order
-  uint32_t* key;
-  uint16_t* cbank;  // [cap] bank of each valid word in bank order
-  uint16_t* mark;   // [cap] bank start markers by raw position, then valid words before it
+  uint16_t* raw;    // [cap] staged raw words; then the arrival slot of each hit in its sort bin;
+                    // then the chunk's words in sorted order
+  uint16_t* kw;     // [cap] word of each valid word (hit) in bank order
+  uint16_t* cbank;  // [cap] bank of each hit
+  uint16_t* mark;   // [cap] bank start markers by raw position, then valid words before it; then
+                    // the sort's bin counters (two per 4 bytes) and bin starts
+  uint16_t* order;  // [cap] hits in bin order
   int cap;
 };
 
-#ifndef UTC_DECODE_BIN_BITS
-#define UTC_DECODE_BIN_BITS 6
-#endif
-// bins of the dense-bank sort: the top kBinBits bits of the word (2^(12 - kBinBits) strips each)
-constexpr int kBinBits = UTC_DECODE_BIN_BITS;
-constexpr int kBins = 1 << kBinBits;
-constexpr int kBinsPerLane = kBins / kWave;
-static_assert(kBins % kWave == 0, "whole bins per lane");
-
 __host__ __device__ inline size_t wave_table_bytes(int S) {
-  return 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(float) * ((size_t)S + 16) +
-         sizeof(uint32_t) * (kBins + 4);
+  return 2 * sizeof(uint32_t) * (size_t)(S + 1) + sizeof(float) * ((size_t)S + 16);
 }
 
 __host__ __device__ inline size_t wave_scratch_bytes(int S, int cap) {
@@ -67,11 +59,11 @@ __device__ inline WaveScratch carve_scratch(char* p, int S, int cap) {
   w.hb = w.off + (S + 1);
   w.u0 = reinterpret_cast<float*>(w.hb + (S + 1));
   w.wt = w.u0 + S;
-  w.bins = reinterpret_cast<uint32_t*>(w.wt + 16);
-  w.key = w.bins + kBins + 4;
-  w.raw = reinterpret_cast<uint16_t*>(w.key + cap);
-  w.cbank = w.raw + cap;
+  w.raw = reinterpret_cast<uint16_t*>(w.wt + 16);   // 4-byte aligned, as are all five arrays
+  w.kw = w.raw + cap;
+  w.cbank = w.kw + cap;
   w.mark = w.cbank + cap;
+  w.order = w.mark + cap;
   w.cap = cap;
   return w;
 }
@@ -264,79 +256,12 @@ __device__ inline uint32_t big_bank(const Geom& g, const uint16_t* __restrict__ 
   return nh;
 }
 
-// Number of the n keys at k below `mine`.
-template <int N>
-__device__ inline uint32_t count_below(const uint32_t* k, uint32_t mine) {
-  uint32_t r = 0;
-#pragma unroll
-  for (int q = 0; q < N; ++q) r += (uint32_t)(k[q] < mine);
-  return r;
-}
-
-// Banks of more than kDenseBank hits are ordered by a counting sort on the top 6 bits of the word
-// (8-strip bins) followed by a rank among the few hits of the same bin, instead of a rank against
-// the whole bank: O(n) rather than O(n^2) per bank.
-constexpr uint32_t kDenseBank = 32;
-
-// Hits [lo, hi) of the chunk (compacted order, keys word << 16 | position in ws.key), all of bank
-// `bank`: each word goes to sorted[lo + its rank in the bank by key].  The chunk's marker array and
-// the bank entries of these hits serve as arrival slots and the bin-ordered hit list meanwhile; the
-// bank entries are restored at the end.  Wave-uniform.
-__device__ inline void dense_bank(uint32_t lo, uint32_t hi, int bank, const WaveScratch& ws,
-                                  uint16_t* sorted)
-{
-  const int lane = lane_id();
-  uint32_t* bins = ws.bins;      // [kBins + 1]
-  uint16_t* slot = ws.mark;      // [k] arrival slot of hit k in its bin
-  uint16_t* order = ws.cbank;    // [lo + i] i-th hit in bin order
-  constexpr int kShift = 32 - kBinBits;
-#pragma unroll
-  for (int q = 0; q < kBinsPerLane; ++q) bins[lane * kBinsPerLane + q] = 0u;
-  if (lane == 0) bins[kBins] = 0u;
-  wave_sync();
-  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
-    slot[k] = (uint16_t)atomicAdd(&bins[ws.key[k] >> kShift], 1u);
-  wave_sync();
-  // bin starts: each lane scans its kBinsPerLane consecutive bins after a scan of the lane sums
-  uint32_t c[kBinsPerLane], csum = 0;
-#pragma unroll
-  for (int q = 0; q < kBinsPerLane; ++q) {
-    c[q] = bins[lane * kBinsPerLane + q];
-    csum += c[q];
-  }
-  uint32_t tot;
-  uint32_t start = wave_excl_scan(csum, &tot);
-  wave_sync();
-#pragma unroll
-  for (int q = 0; q < kBinsPerLane; ++q) {
-    bins[lane * kBinsPerLane + q] = start;
-    start += c[q];
-  }
-  if (lane == 0) bins[kBins] = tot;
-  wave_sync();
-  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave)
-    order[lo + bins[ws.key[k] >> kShift] + slot[k]] = (uint16_t)k;
-  wave_sync();
-  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave) {
-    const uint32_t mine = ws.key[k];
-    const uint32_t bin = mine >> kShift;
-    const uint32_t s0 = bins[bin], s1 = bins[bin + 1];
-    uint32_t rank = s0;   // hits of the lower bins
-    // the other hits of the bin, four at a time (their list entries, then their keys, read
-    // together); a slot past the bin stands for the hit itself, which is not below its own key
-    for (uint32_t j = s0; j < s1; j += 4) {
-      uint32_t o[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = j + q < s1 ? (uint32_t)order[lo + j + q] : k;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rank += ws.key[o[q]] < mine;
-    }
-    sorted[lo + rank] = (uint16_t)(mine >> 16);
-  }
-  wave_sync();
-  // the bank entries of these hits again (the write-out reads the bank of each sorted slot there)
-  for (uint32_t k = lo + (uint32_t)lane; k < hi; k += kWave) order[k] = (uint16_t)bank;
-  wave_sync();
+// Sort bin of hit k (Section IV: hits of a sector are kept in strip order).  Each bank of the chunk
+// is cut into as many equal bins of the word's strip and fraction bits (word >> 4, 12 bits) as it
+// has hits, numbered from the bank's first hit on: bins of lower banks and lower words come first.
+__device__ inline uint32_t hit_bin(const WaveScratch& ws, uint32_t bank, uint32_t word) {
+  const uint32_t lo = ws.hb[bank], m = ws.hb[bank + 1] - lo;
+  return lo + (((word >> 4) * m) >> 12);
 }
 
 // Compaction, sort and store of the unit's hits, first hit `base`.
@@ -448,7 +373,7 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
         const uint32_t pos = run + lanes_before(m);
         if (i < n) ws.mark[i] = (uint16_t)pos;
         if (valid) {
-          ws.key[pos] = (v[k] << 16) | pos;
+          ws.kw[pos] = (uint16_t)v[k];
           ws.cbank[pos] = (uint16_t)(b - 1);
         }
         run += (uint32_t)__popcll(m);
@@ -463,44 +388,117 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
     wave_sync();
     for (int b = c0 + lane; b < c1; b += kWave) hit_offsets[b0 + b] = base + local + ws.hb[b];
 
-    // each hit's rank in its bank by (word, position): sorted by word value, ties in bank order;
-    // the word goes to its sorted slot of the chunk in LDS (the staged raw words are no longer
-    // needed).  Banks of more than kDenseBank hits are ranked afterwards by dense_bank.
-    uint16_t* sorted = ws.raw;
-    for (uint32_t k = lane; k < nh; k += kWave) {
-      const int bk = ws.cbank[k];
-      const uint32_t lo = ws.hb[bk], hi = ws.hb[bk + 1];
-      if (hi - lo > kDenseBank) continue;
-      const uint32_t mine = ws.key[k];
-      // keys of the bank below this hit's, compared 16, 8 and 4 at a time (independent LDS reads
-      // in flight; the central banks of an event hold tens of hits), then the last up to three
-      uint32_t rank = 0;
-      uint32_t j = lo;
-      for (; j + 16 <= hi; j += 16) rank += count_below<16>(ws.key + j, mine);
-      if (j + 8 <= hi) {
-        rank += count_below<8>(ws.key + j, mine);
-        j += 8;
+    // each hit's rank in its bank by (word, position): a counting sort of the chunk's hits on their
+    // bins (hit_bin), then a rank among the few hits of the same bin; the word goes to its sorted
+    // slot of the chunk.  Four groups of 64 hits per pass, their LDS reads issued together.
+    constexpr int G = 4;
+    const uint32_t pad_bank = (uint32_t)c0;   // a valid bank index for lanes past the last hit
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(ws.mark);   // bin counters, 16 bits each
+    for (uint32_t i = lane; i < (nh + 1) / 2; i += kWave) cnt[i] = 0u;
+    wave_sync();
+    for (uint32_t k0 = 0; k0 < nh; k0 += G * kWave) {
+      uint32_t bk[G], w[G], b[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
+        bk[q] = k < nh ? (uint32_t)ws.cbank[k] : pad_bank;
+        w[q] = k < nh ? (uint32_t)ws.kw[k] : 0u;
       }
-      if (j + 4 <= hi) {
-        rank += count_below<4>(ws.key + j, mine);
-        j += 4;
+#pragma unroll
+      for (int q = 0; q < G; ++q) b[q] = hit_bin(ws, bk[q], w[q]);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
+        if (k < nh) {
+          const uint32_t sh = 16u * (b[q] & 1u);
+          ws.raw[k] = (uint16_t)(atomicAdd(&cnt[b[q] >> 1], 1u << sh) >> sh);
+        }
       }
-      if (j < hi) rank += ws.key[j] < mine;
-      if (j + 1 < hi) rank += ws.key[j + 1] < mine;
-      if (j + 2 < hi) rank += ws.key[j + 2] < mine;
-      sorted[lo + rank] = (uint16_t)(mine >> 16);
     }
     wave_sync();
-    // the dense banks of the chunk, one after the other (found 64 banks at a time by a ballot)
-    for (int b0c = c0; b0c < c1; b0c += kWave) {
-      const int b = b0c + lane;
-      uint64_t dense = ballot(b < c1 && ws.hb[b + 1] - ws.hb[b] > kDenseBank);
-      while (dense) {
-        const int bd = b0c + (int)__builtin_ctzll(dense);
-        dense &= dense - 1;
-        dense_bank(ws.hb[bd], ws.hb[bd + 1], bd, ws, sorted);
+    // bin starts, in place: lane l scans the bins [l*L, l*L + L) after a scan of the lane sums
+    {
+      const uint32_t L = (nh + kWave - 1) / kWave;
+      const uint32_t f = (uint32_t)lane * L;
+      const uint32_t e = f + L < nh ? f + L : nh;
+      uint32_t sum = 0;
+      for (uint32_t i = f; i < e; i += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = i + q < e ? (uint32_t)ws.mark[i + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum += c[q];
+      }
+      uint32_t tot;
+      uint32_t run = wave_excl_scan(sum, &tot);
+      for (uint32_t i = f; i < e; i += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = i + q < e ? (uint32_t)ws.mark[i + q] : 0u;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (i + q < e) ws.mark[i + q] = (uint16_t)run;
+          run += c[q];
+        }
       }
     }
+    wave_sync();
+    // the hits of each bin in bank order (arrival slots are in no particular order)
+    for (uint32_t k0 = 0; k0 < nh; k0 += G * kWave) {
+      uint32_t bk[G], w[G], sl[G], b[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
+        bk[q] = k < nh ? (uint32_t)ws.cbank[k] : pad_bank;
+        w[q] = k < nh ? (uint32_t)ws.kw[k] : 0u;
+        sl[q] = k < nh ? (uint32_t)ws.raw[k] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) b[q] = ws.mark[hit_bin(ws, bk[q], w[q])];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
+        if (k < nh) ws.order[b[q] + sl[q]] = (uint16_t)k;
+      }
+    }
+    wave_sync();
+    uint16_t* sorted = ws.raw;   // the arrival slots are no longer needed
+    for (uint32_t k0 = 0; k0 < nh; k0 += G * kWave) {
+      uint32_t bk[G], w[G], s0[G], s1[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
+        bk[q] = k < nh ? (uint32_t)ws.cbank[k] : pad_bank;
+        w[q] = k < nh ? (uint32_t)ws.kw[k] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t b = hit_bin(ws, bk[q], w[q]);
+        s0[q] = ws.mark[b];
+        s1[q] = b + 1 < nh ? (uint32_t)ws.mark[b + 1] : nh;
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
+        if (k < nh) {
+          // the hits of the bin below (word, position) = (w, k), four at a time; a slot past the
+          // bin stands for the hit itself, which is not below itself
+          uint32_t rank = s0[q];
+          for (uint32_t j = s0[q]; j < s1[q]; j += 4) {
+            uint32_t o[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = j + r < s1[q] ? (uint32_t)ws.order[j + r] : k;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint32_t x = ws.kw[o[r]];
+              rank += (uint32_t)((x < w[q]) | ((x == w[q]) & (o[r] < k)));
+            }
+          }
+          sorted[rank] = (uint16_t)w[q];
+        }
+      }
+    }
+    wave_sync();
     // decode in sorted order and store: the 64 lanes write 64 consecutive hits of each array,
     // four such groups per pass (their LDS reads in flight together).  Sorting stays inside the
     // banks, so sorted slot p belongs to the bank of compacted hit p.
