@@ -861,6 +861,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   const float g_yb = ev.yb_glb ? -INFINITY : g.y_begin, g_ye = ev.yb_glb ? INFINITY : g.y_end;
   uint32_t umask = 0;
   float wm = 0.0f;
+  float rz = 0.0f;   // largest |x - xs| over the usable window slots
   for (int j0 = 0; j0 < wn; j0 += 8) {
     float uu[8], ww[8], yb[8], ye[8];
 #pragma unroll
@@ -884,20 +885,19 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
     for (int q = 0; q < 8; ++q) {
       if (j0 + q < wn) {
         const float w = (yb[q] <= yl && yl <= ye[q]) ? ww[q] : -1.0f;
-        s.tm[tile_at(t, l, j0 + q)] = uu[q] + yl * g.dxdy[l];
+        const float xm = uu[q] + yl * g.dxdy[l];
+        s.tm[tile_at(t, l, j0 + q)] = xm;
         s.tw[tile_at(t, l, j0 + q)] = w;
         if (w >= 0.0f) {
           umask |= 1u << (j0 + q);
           wm = fmaxf(wm, w);
+          rz = fmaxf(rz, fabsf(xm - xs));
         }
       }
     }
   }
   // per-track bound Z of |q| sqrt(Saa) for the pruning margin: the largest |r| / a over the
   // usable window slots and the sum of the largest usable weight times a^2, over the four layers
-  float rz = 0.0f;
-  for (uint32_t mm = umask; mm; mm &= mm - 1u)
-    rz = fmaxf(rz, fabsf(s.tm[tile_at(t, l, (int)__builtin_ctz(mm))] - xs));
   rz *= g.inv_a_up[l];
   float kz = wm * g.a_kick[l] * g.a_kick[l];
   rz = fmaxf(rz, __shfl_xor(rz, 1, kWave));
