@@ -96,6 +96,46 @@ def test_banks_larger_than_the_lds_chunk(n_extra, tile):
     assert_decode_equal(h, d)
 
 
+def _insert_words(b, bank, extra):
+    """Append the words `extra` to bank `bank` of batch b (offsets of the later banks shifted)."""
+    off = b.bank_offsets.astype(np.int64)
+    b.words = np.concatenate([b.words[:off[bank + 1]], np.asarray(extra, np.uint16), b.words[off[bank + 1]:]])
+    off[bank + 1:] += len(extra)
+    b.bank_offsets = off.astype(np.uint32)
+
+
+@pytest.mark.parametrize("tile", [0, 4])
+def test_crowded_sort_bins(tile):
+    """Banks that fit the decoder's LDS chunk but crowd its sort bins (each bank is cut into as
+    many bins of the word's strip and fraction as it has hits): every word of a bank equal, all
+    hits on two strips, hits only at both ends of the strip range (the first and the last bin),
+    a one-hit bank and a bank of padding words only, in the units of two events; at the default
+    tile the units are staged whole, at 4 KiB they are cut into chunks between banks."""
+    b = synth.generate("tiny", n_events=3, seed=36, with_truth=False)
+    S = b.detector.n_sectors
+    rng = np.random.default_rng(36)
+    w = lambda strip, frac, size: ((np.asarray(strip) << 7) | (np.asarray(frac) << 4) | np.asarray(size))
+    n = 160
+    cases = {
+        (0 * 4 + 1) * S + 3: np.full(n, w(200, 5, 3)),                                   # all equal
+        (0 * 4 + 1) * S + 4: w(rng.choice([17, 18], n), rng.integers(0, 8, n), rng.integers(1, 16, n)),
+        (0 * 4 + 1) * S + 9: w(rng.choice([0, 511], n), rng.choice([0, 7], n), rng.integers(1, 3, n)),
+        (0 * 4 + 1) * S + 10: w([300], [2], [4]),                                          # one hit
+        (0 * 4 + 1) * S + 11: w(rng.integers(0, 512, 40), rng.integers(0, 8, 40), 0),     # padding only
+        (2 * 4 + 3) * S + 0: w(rng.integers(250, 254, n), rng.integers(0, 8, n),
+                               np.where(rng.random(n) < 0.2, 0, rng.integers(1, 16, n))),
+        (2 * 4 + 3) * S + 31: np.full(n, w(511, 7, 15)),                                  # the last bin
+    }
+    # insert from the last bank backwards so that the earlier offsets stay valid
+    for bank in sorted(cases, reverse=True):
+        _insert_words(b, bank, cases[bank].astype(np.uint16))
+    print(f"[limits crowded bins] tile={tile} words={b.n_words}", flush=True)
+    h, r, *_ = gpu_run(b, launch_decode=dict(block=256, grid=0, tile=tile), find=False)
+    d, c = oracle_run(b, find=False)
+    assert d["flags"] == 0 and h["error_flags"] == 0
+    assert_decode_equal(h, d)
+
+
 def test_layer_beyond_16_bit_windows():
     """Event 0, layer 0 holds 40000 hits (five banks of 8000): the search flags the overflow and
     gives that event's tracks no candidates; the other event is searched as usual."""
