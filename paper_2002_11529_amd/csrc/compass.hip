@@ -152,32 +152,30 @@ k_compass(Geom g, CPar p, int n_events, const uint32_t* __restrict__ hit_offsets
     ev.stride = staged ? 1u : (ncoarse > 0 ? stride : 0u);
     const uint32_t t0 = velo_offsets[e], t1 = velo_offsets[e + 1];
     const uint32_t ngroups = (t1 - t0 + kGroupTracks - 1) / kGroupTracks;
-    // a wave claims its next group before searching the current one, so that the next group's
-    // VELO states are loaded meanwhile
+    // a wave claims its next group before searching the current one (the group's VELO states are
+    // loaded after the search: held in registers across it they cost more in spilled registers
+    // than their load latency)
     uint32_t grp = (uint32_t)wid;
     uint32_t nxt = grp < ngroups ? claim_group(s_next) : ngroups;
     LaneState st = load_state(io, t0 + grp * kGroupTracks, t1);
     if (staged_w) {
       while (grp < ngroups) {
-        const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
         compass_group<true, true, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
-        st = next;
+        st = load_state(io, t0 + nxt * kGroupTracks, t1);
         grp = nxt;
         nxt = grp < ngroups ? claim_group(s_next) : ngroups;
       }
     } else if (staged) {
       while (grp < ngroups) {
-        const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
         compass_group<true, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
-        st = next;
+        st = load_state(io, t0 + nxt * kGroupTracks, t1);
         grp = nxt;
         nxt = grp < ngroups ? claim_group(s_next) : ngroups;
       }
     } else {
       while (grp < ngroups) {
-        const LaneState next = load_state(io, t0 + nxt * kGroupTracks, t1);
         compass_group<false, false, kGreedy>(g, p, ev, gs, t0 + grp * kGroupTracks, t1, io, st);
-        st = next;
+        st = load_state(io, t0 + nxt * kGroupTracks, t1);
         grp = nxt;
         nxt = grp < ngroups ? claim_group(s_next) : ngroups;
       }
