@@ -71,7 +71,7 @@ struct GroupScratch {
   unsigned long long* best;  // [16] selection key minimum
   unsigned long long* lbk;   // [16] seed choice of the batch: two-anchor bound << 32 | lane
   uint32_t* umask;    // [64] usable window slots (strip covers the track's y)
-  float* wmax;        // [64] largest weight of the usable slots
+  uint32_t* wfirst;   // [64] first hit of each window (event-local), kept here across the search
   uint32_t* poff;     // [17] pair offsets of the tracks
   uint32_t* bp;       // [128] anchor pairs that passed the slope test: t | jA<<8 | jB<<16 (a batch
                       // of at most 64 at the front; in the pruned 4-hit search the pairs kept so
@@ -101,8 +101,8 @@ __device__ inline GroupScratch carve_group(char* p, int max_hits, bool greedy) {
   s.best = reinterpret_cast<unsigned long long*>(p);
   s.lbk = s.best + kGroupTracks;
   s.umask = reinterpret_cast<uint32_t*>(s.lbk + kGroupTracks);
-  s.wmax = reinterpret_cast<float*>(s.umask + 64);
-  s.tm = s.wmax + 64;
+  s.wfirst = s.umask + 64;
+  s.tm = reinterpret_cast<float*>(s.wfirst + 64);
   s.tw = s.tm + 64 * max_hits;
   s.xs = s.tw + 64 * max_hits;
   s.tx = s.xs + 64;
@@ -784,7 +784,8 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   if (l == 0 || l == kLayers - 1)
     ok = (g.y_begin <= yl && yl <= g.y_end) && (g.u_min <= up && up <= u_max);
   const uint64_t okm = ballot(ok);
-  const bool active = has && !ev.overflow && ((okm >> (4 * t)) & 1ull) && ((okm >> (4 * t + 3)) & 1ull);
+  // inside at the track's layer-0 lane (4t) and layer-3 lane (4t + 3)
+  const bool active = has && !ev.overflow && ((okm >> (lane & ~3)) & 9ull) == 9ull;
 
   // window (Section V-A): central sector and neighbours, [up - W, up + W], nearest max_hits hits
   uint32_t wf = 0;
@@ -906,7 +907,7 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   kz = kz + __shfl_xor(kz, 2, kWave);
   if (l == 0) s.tz[t] = p.prune ? rz * __builtin_amdgcn_sqrtf(kz) * 1.001f : INFINITY;
   s.umask[lane] = umask;
-  s.wmax[lane] = wm;
+  s.wfirst[lane] = wf;
   if constexpr (kGreedy) {
     // walk order of the window (Section V-B: the combined sector ranges with the central sector
     // first, then the neighbours at growing distance, the left one first; ascending x inside a
@@ -943,6 +944,8 @@ __device__ inline void compass_group(const Geom& g, const CPar& p, const EventVi
   const unsigned long long key = active ? s.best[t] : kNoKey;
   const bool found = key != kNoKey;
   const uint32_t code = found ? (uint32_t)((key >> (6 * (3 - l))) & 63ull) : 0u;
+  wf = s.wfirst[lane];   // read back rather than held in a register across the search
+  wn = s.nwin[lane];
   if (has) {
     io.hit_idx[(int64_t)trk * 4 + l] = code ? (int32_t)(ev.first + wf + code - 1) : -1;
     if (io.windows) {
