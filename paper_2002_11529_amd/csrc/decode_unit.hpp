@@ -481,18 +481,16 @@ __device__ inline void unit_write(const Geom& g, const uint16_t* __restrict__ wo
       for (int q = 0; q < G; ++q) {
         const uint32_t k = k0 + (uint32_t)(q * kWave + lane);
         if (k < nh) {
-          // the hits of the bin below (word, position) = (w, k), four at a time; a slot past the
-          // bin stands for the hit itself, which is not below itself
+          // the hits of the bin below (word, position) = (w, k), compared as word << 16 | position,
+          // four at a time; a slot past the bin stands for the hit itself, which is not below itself
+          const uint32_t mine = (w[q] << 16) | k;
           uint32_t rank = s0[q];
           for (uint32_t j = s0[q]; j < s1[q]; j += 4) {
             uint32_t o[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) o[r] = j + r < s1[q] ? (uint32_t)ws.order[j + r] : k;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const uint32_t x = ws.kw[o[r]];
-              rank += (uint32_t)((x < w[q]) | ((x == w[q]) & (o[r] < k)));
-            }
+            for (int r = 0; r < 4; ++r) rank += (((uint32_t)ws.kw[o[r]] << 16) | o[r]) < mine;
           }
           sorted[rank] = (uint16_t)w[q];
         }
