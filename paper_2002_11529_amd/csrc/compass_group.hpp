@@ -283,7 +283,6 @@ __device__ inline void completion_ranges(const Geom& g, const CPar& p, const Gro
 // values).
 struct AnchorFit {
   double S, N, C;    // k_A + k_B, sum w a r, chi2_AB * S^2
-  float qab;         // approximate N / S (seed choice only)
 };
 
 __device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int t, int A, int B,
@@ -297,7 +296,6 @@ __device__ inline AnchorFit anchor_fit(const Geom& g, const GroupScratch& s, int
   f.N = wA * aA * rA + wB * aB * rB;
   const double eA = rA * f.S - aA * f.N, eB = rB * f.S - aB * f.N;
   f.C = wA * eA * eA + wB * eB * eB;
-  f.qab = __fdividef((float)f.N, (float)f.S);
   return f;
 }
 
@@ -528,44 +526,79 @@ __device__ inline void propose_seed(const Geom& g, const GroupScratch& s, int tt
   const float rAaB = (s.tm[oA] - s.xs[tt * 4 + A]) * aB;
   const float kA = wA * aA * aA;
   const float xsB = s.xs[tt * 4 + B];
-  unsigned long long k = kNoKey;
+  uint32_t best = ~0u, arg = 0;   // lowest |chi2| bits, and its slot (the lowest on a tie)
   for (uint32_t mm = rem; mm; mm &= mm - 1u) {
     const uint32_t jB = (uint32_t)__builtin_ctz(mm);
     const int oB = tile_at(tt, B, (int)jB);
     const float wB = s.tw[oB];
     const float d = rAaB - (s.tm[oB] - xsB) * aA;
-    const float c2 = __fdividef(wA * wB * d * d, kA + wB * aB * aB);
-    k = min(k, ((unsigned long long)__float_as_uint(fabsf(c2)) << 32) | (jA << 8) | jB);
+    const uint32_t c2 = __float_as_uint(fabsf(__fdividef(wA * wB * d * d, kA + wB * aB * aB)));
+    if (c2 < best) {
+      best = c2;
+      arg = jB;
+    }
   }
-  if (k != kNoKey) atomicMin(&s.lbk[tt], k);
+  if (rem) atomicMin(&s.lbk[tt], ((unsigned long long)best << 32) | (jA << 8) | arg);
 }
 
-// Each track's proposed seed pair (lanes 0..15, track = lane) is completed with the compatible hits
-// nearest to its two-anchor fit; when both completion layers have one this is a 4-hit candidate of
-// the track, and its key goes into the track's minimum, so that its chi2 bounds the rest.
+// Completion slots of a passing pair in one layer Cl (one of the two ranges completion_ranges
+// searches together).
+__device__ inline uint32_t completion_range(const Geom& g, const CPar& p, const GroupScratch& s, int t,
+                                            int A, int Cl, float mA, float slope) {
+  float lo, hi;
+  completion_bounds(g, p, s, t, A, Cl, mA, slope, lo, hi);
+  const uint32_t n = (uint32_t)s.nwin[t * 4 + Cl];
+  uint32_t a0 = 0, a1 = n, b0 = 0, b1 = n;
+  while (a0 < a1 || b0 < b1) {
+    const uint32_t am = a0 + ((a1 - a0) >> 1), bm = b0 + ((b1 - b0) >> 1);
+    const float xa = a0 < a1 ? s.tm[tile_at(t, Cl, (int)am)] : 0.0f;
+    const float xb = b0 < b1 ? s.tm[tile_at(t, Cl, (int)bm)] : 0.0f;
+    if (a0 < a1) { if (xa >= lo) a1 = am; else a0 = am + 1; }
+    if (b0 < b1) { if (xb > hi) b1 = bm; else b0 = bm + 1; }
+  }
+  return range_mask(a0, b0);
+}
+
+// Each track's proposed seed pair is completed with the compatible hits nearest to its two-anchor
+// fit; when both completion layers have one this is a 4-hit candidate of the track, and its key
+// goes into the track's minimum, so that its chi2 bounds the rest.  Four lanes per track (lane
+// 4t + l): lanes l = 0 and 1 search completion layers C1 and C2, lane l = 0 fits the candidate.
+// want_lane is read on the track's lane 4t.  Every lane calls it.
 __device__ inline void seed_tracks(const Geom& g, const CPar& p, const GroupScratch& s, int A, int B,
-                                   int C1, int C2, float inv_dz_ab, bool want_track) {
-  const int t = lane_id();
-  if (t >= kGroupTracks || !want_track) return;
+                                   int C1, int C2, float inv_dz_ab, bool want_lane) {
+  const int lane = lane_id();
+  const int t = lane >> 2, l = lane & 3;
   const unsigned long long key = s.lbk[t];
-  if (key == kNoKey) return;
+  const bool go = __shfl((int)want_lane, lane & ~3, kWave) != 0 && key != kNoKey;
   const int jA = (int)((key >> 8) & 0xFFu), jB = (int)(key & 0xFFu);
-  const float mA = s.tm[tile_at(t, A, jA)];
-  const float slope = (s.tm[tile_at(t, B, jB)] - mA) * inv_dz_ab;
-  uint32_t m1, m2;
-  completion_ranges(g, p, s, t, A, C1, C2, mA, slope, m1, m2);
-  m1 &= s.umask[t * 4 + C1];
-  m2 &= s.umask[t * 4 + C2];
-  if (!m1 || !m2) return;
-  const AnchorFit af = anchor_fit(g, s, t, A, B, jA, jB);
-  uint32_t code[4];
-  code[A] = (uint32_t)jA + 1u;
-  code[B] = (uint32_t)jB + 1u;
-  code[C1] = nearest_slot(g, s, t, C1, m1, af.qab) + 1u;
-  code[C2] = nearest_slot(g, s, t, C2, m2, af.qab) + 1u;
-  float qs, cs;
-  fit_codes(g, s, t, code, qs, cs);
-  s.best[t] = min(s.best[t], make_key(4, cs, code));
+  uint32_t m = 0, slot = 0;
+  if (go && l < 2) {
+    const int Cl = l == 0 ? C1 : C2;
+    const int oA = tile_at(t, A, jA), oB = tile_at(t, B, jB);
+    const float mA = s.tm[oA];
+    const float slope = (s.tm[oB] - mA) * inv_dz_ab;
+    m = completion_range(g, p, s, t, A, Cl, mA, slope) & s.umask[t * 4 + Cl];
+    if (m) {
+      // the two-anchor fit's q in binary32 (it only steers the choice of the completion hits)
+      const float aA = g.a_kick[A], aB = g.a_kick[B];
+      const float wA = s.tw[oA], wB = s.tw[oB];
+      const float qab = __fdividef(wA * aA * (mA - s.xs[t * 4 + A]) + wB * aB * (s.tm[oB] - s.xs[t * 4 + B]),
+                                   wA * aA * aA + wB * aB * aB);
+      slot = nearest_slot(g, s, t, Cl, m, qab);
+    }
+  }
+  const uint32_t m2 = (uint32_t)__shfl((int)m, lane | 1, kWave);      // layer C2, from lane 4t + 1
+  const uint32_t slot2 = (uint32_t)__shfl((int)slot, lane | 1, kWave);
+  if (go && l == 0 && m && m2) {
+    uint32_t code[4];
+    code[A] = (uint32_t)jA + 1u;
+    code[B] = (uint32_t)jB + 1u;
+    code[C1] = slot + 1u;
+    code[C2] = slot2 + 1u;
+    float qs, cs;
+    fit_codes(g, s, t, code, qs, cs);
+    s.best[t] = min(s.best[t], make_key(4, cs, code));
+  }
 }
 
 // Whether anchor pair (jA, jB) of track tt can hold the track's selected 4-hit candidate: not when
@@ -642,7 +675,7 @@ __device__ inline void run_direction(const Geom& g, const CPar& p, const GroupSc
         if (it < total) propose_seed(g, s, tt, A, B, it - s.poff[tt], s.irem[it]);
       }
       wave_sync();
-      seed_tracks(g, p, s, A, B, C1, C2, inv_dz_ab, __shfl((int)want_lane, (lane & 15) * 4, kWave) != 0);
+      seed_tracks(g, p, s, A, B, C1, C2, inv_dz_ab, want_lane);
       wave_sync();
     }
   }
