@@ -69,7 +69,9 @@ struct GroupScratch {
   float* tx;          // [16] VELO slope tx of each track
   int32_t* nwin;      // [64] window sizes
   unsigned long long* best;  // [16] selection key minimum
-  unsigned long long* lbk;   // [16] seed choice of the batch: two-anchor bound << 32 | lane
+  unsigned long long* lbk;   // [16] per track: the seed pair proposed so far (two-anchor chi2 bits
+                             // << 32 | anchor-A slot << 8 | anchor-B slot), or, in the paper's
+                             // search, the number of tracklets found
   uint32_t* umask;    // [64] usable window slots (strip covers the track's y)
   uint32_t* wfirst;   // [64] first hit of each window (event-local), kept here across the search
   uint32_t* poff;     // [17] pair offsets of the tracks
